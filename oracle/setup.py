@@ -1,0 +1,43 @@
+"""Turn a workload description (plain dict of numpy fields) into oracle inputs.
+
+TEST INFRASTRUCTURE ONLY (see the package docstring).
+"""
+import numpy as np
+import torch
+
+from . import interaction as src
+from . import transport as tr
+from .geometry import FlatCartesian
+from .grid import GeodesicGrid
+from .step import Problem
+
+F64 = torch.float64
+BC = {"periodic": tr.PERIODIC, "outflow": tr.OUTFLOW, "zero_incoming": tr.ZERO_INCOMING}
+MODEL = {"kirchhoff_const": src.KIRCHHOFF_CONST, "brems": src.BREMS,
+         "fixed_emissivity": src.FIXED_EMISSIVITY}
+
+
+def _t(x):
+    return None if x is None else torch.as_tensor(np.asarray(x, dtype=np.float64))
+
+
+def build_flat(wl, grid=None, limiter=tr.LIM_MC):
+    """Problem, initial intensity [Ns,*n] (isotropic I0_iso) and temperature."""
+    grid = grid or GeodesicGrid(wl["generation"], wl["weights"])
+    geo = FlatCartesian(wl["n"], wl["xlo"], wl["xhi"], grid)
+    shape = tuple(wl["n"])
+    rho = _t(wl["rho"])
+    if wl.get("u") is None:
+        u_hat = torch.zeros((4,) + shape, dtype=F64)
+        u_hat[0] = 1.0
+    else:
+        u_hat = geo.u_hat(_t(wl["u"]))
+    v = u_hat[1:] / u_hat[0]
+    bc = tuple(BC[b] for b in wl["bc"])
+    pb = Problem(geo=geo, rho=rho, u_hat=u_hat, v=v, model=MODEL[wl["model"]],
+                 gamma=wl["gamma"], kappa_a=_t(wl.get("kappa_a")), kappa_s=_t(wl.get("kappa_s")),
+                 j=_t(wl.get("j")), C_a=wl.get("C_a", 1.0), C_s=wl.get("C_s", 1.0),
+                 bc_lo=bc, bc_hi=bc, limiter=limiter)
+    I0 = _t(wl["I0_iso"]).unsqueeze(0).expand((grid.ns,) + shape).clone()
+    T0 = _t(wl["T"]).clone()
+    return pb, I0, T0

@@ -1,0 +1,562 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+None of these compares the oracle with itself: each check is a closed form,
+an invariant, a special case that reduces to a textbook result, an
+independent library routine, or a value fixed by the paper's own setup
+(fixtures under tests/golden/ carry their citation).
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+import torch
+from scipy.spatial import ConvexHull
+
+import workloads as W
+from oracle import interaction as src
+from oracle import step as st
+from oracle import transport as tr
+from oracle.geometry import FlatCartesian
+from oracle.grid import GeodesicGrid
+from oracle.setup import build_flat
+
+F64 = torch.float64
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def gold(name):
+    with open(os.path.join(GOLD, name)) as f:
+        return json.load(f)
+
+
+# --------------------------------------------------------------------------
+# P1  geodesic grid (Sec. 3.3)
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("g", [0, 1, 2, 3])
+def test_grid_counts_and_degrees(g):
+    ref = gold("geodesic_counts.json")
+    G = GeodesicGrid(g)
+    assert G.ns == ref["n_cells"][g]
+    assert len(G.edges) == 3 * G.ns - 6
+    assert len(G.tris) == 2 * G.ns - 4
+    assert (G.degree == 5).sum() == ref["n_pentagons"]
+    assert set(G.degree.tolist()) <= {5, 6}
+    assert np.allclose(np.linalg.norm(G.n, axis=1), 1.0, atol=1e-15)
+
+
+@pytest.mark.parametrize("g", [0, 1, 2, 3])
+def test_grid_is_spherical_delaunay(g):
+    """The triangulation equals the convex hull of the points (the spherical
+    Delaunay triangulation), computed independently by Qhull."""
+    G = GeodesicGrid(g)
+    hull = ConvexHull(G.n)
+    mine = {tuple(sorted(t)) for t in G.tris.tolist()}
+    if g == 0:
+        theirs = {tuple(sorted(t)) for t in hull.simplices.tolist()}
+        assert mine == theirs
+    else:
+        # coplanar facets may be split either way by Qhull only for degenerate
+        # quadruples; the geodesic grid has none, so the sets agree exactly
+        theirs = {tuple(sorted(t)) for t in hull.simplices.tolist()}
+        assert mine == theirs
+
+
+@pytest.mark.parametrize("g", [0, 1, 2, 3])
+@pytest.mark.parametrize("weights", ["voronoi", "equal"])
+def test_grid_quadrature_identities(g, weights):
+    """Sum w = 4 pi, sum w n = 0, sum w n n = (4 pi / 3) delta: exact for this
+    centrally symmetric, icosahedrally invariant point set (Schur's lemma)."""
+    G = GeodesicGrid(g, weights)
+    w, n = G.w, G.n
+    assert abs(w.sum() - 4 * math.pi) < 1e-13
+    assert np.abs((w[:, None] * n).sum(0)).max() < 1e-14
+    M2 = np.einsum("s,si,sj->ij", w, n, n)
+    assert np.abs(M2 - 4 * math.pi / 3 * np.eye(3)).max() < 1e-13
+
+
+@pytest.mark.parametrize("g", [1, 2, 3])
+def test_voronoi_area_by_girard(g):
+    """Each Voronoi cell's solid angle equals its spherical excess (Girard's
+    theorem: sum of interior angles - (k - 2) pi), computed here from the
+    polygon's corner angles, independently of the oracle's triangle fan."""
+    G = GeodesicGrid(g)
+    cc = G.circum
+    inc = [[] for _ in range(G.ns)]
+    for t, tri in enumerate(G.tris):
+        for v in tri:
+            inc[v].append(t)
+    for s in range(G.ns):
+        p = G.n[s]
+        ref = np.array([1.0, 0, 0]) if abs(p[0]) < 0.9 else np.array([0, 1.0, 0])
+        e1 = ref - p * np.dot(ref, p)
+        e1 /= np.linalg.norm(e1)
+        e2 = np.cross(p, e1)
+        ring = sorted(inc[s], key=lambda t: math.atan2(cc[t] @ e2, cc[t] @ e1))
+        k = len(ring)
+        ang = 0.0
+        for i in range(k):
+            a, b, c = cc[ring[i - 1]], cc[ring[i]], cc[ring[(i + 1) % k]]
+            # interior angle at vertex b between great-circle arcs b->a, b->c
+            ta = a - b * np.dot(a, b)
+            tc = c - b * np.dot(c, b)
+            ang += math.acos(np.clip(np.dot(ta, tc) / np.linalg.norm(ta) / np.linalg.norm(tc), -1, 1))
+        assert abs((ang - (k - 2) * math.pi) - G.area[s]) < 1e-12
+
+
+def test_voronoi_edges():
+    """Edges: every Voronoi edge separates two neighbours; its normal points
+    from s to s'.  For a polygon of great-circle arcs on the unit sphere the
+    divergence theorem gives sum_e L_e u_e = -2 integral x dA, which for a
+    small cell is -2 (area) n_s up to O(cell radius^2)."""
+    G = GeodesicGrid(2)
+    acc = np.zeros((G.ns, 3))
+    for (s, t), L, m, u in zip(G.edges, G.dlam, G.emid, G.enorm):
+        assert abs(np.dot(m, G.n[s]) - np.dot(m, G.n[t])) < 1e-14
+        assert np.dot(u, G.n[t] - G.n[s]) > 0
+        assert abs(np.dot(u, m)) < 1e-14
+        acc[s] += L * u
+        acc[t] -= L * u
+    ref = -2.0 * G.area[:, None] * G.n
+    assert np.abs(acc - ref).max() < 0.02 * 2.0 * G.area.max()
+
+
+# --------------------------------------------------------------------------
+# P3  Lorentz boost (Sec. 2.1.2, Eq. fluid_to_coordinate)
+# --------------------------------------------------------------------------
+def _boost_matrix(u):
+    """The boost of Eq. fluid_to_coordinate.  Its first row (u^0, -u^i) and
+    spatial block are as printed; the first column is taken as -u^i (as
+    printed, +u_i, the matrix would neither preserve eta nor bring u to rest,
+    so the sign there is read as a typo; only the first row enters the
+    method)."""
+    L = np.zeros((4, 4))
+    L[0, 0] = u[0]
+    L[0, 1:] = -u[1:]
+    L[1:, 0] = -u[1:]
+    L[1:, 1:] = np.eye(3) + np.outer(u[1:], u[1:]) / (1 + u[0])
+    return L
+
+
+def test_boost_matrix_and_first_row():
+    rng = np.random.default_rng(1)
+    eta = np.diag([-1.0, 1, 1, 1])
+    G = GeodesicGrid(2)
+    for _ in range(5):
+        us = rng.normal(size=3) * 0.7
+        u = np.concatenate([[math.sqrt(1 + us @ us)], us])
+        L = _boost_matrix(u)
+        # Lambda^T eta Lambda = eta; the fluid is at rest in the barred frame
+        assert np.abs(L.T @ eta @ L - eta).max() < 1e-13
+        # the oracle's nbar^0 equals the time component of the boosted direction
+        diag = {}
+        It = torch.ones((G.ns, 1), dtype=F64)
+        src.interact(It, torch.ones(1, dtype=F64), torch.ones(1, dtype=F64), torch.ones(1, dtype=F64),
+                     torch.tensor(u, dtype=F64).reshape(4, 1), torch.ones(1, dtype=F64),
+                     torch.tensor(G.n), torch.tensor(G.w), 0.1, src.FIXED_EMISSIVITY, 5 / 3,
+                     torch.ones(1, dtype=F64), torch.zeros(1, dtype=F64), torch.zeros(1, dtype=F64),
+                     1.0, 1.0, 5e-4, diag=diag)
+        n4 = np.concatenate([np.ones((G.ns, 1)), G.n], axis=1)
+        nb = (L @ n4.T)[0]
+        assert np.abs(diag["nb0"][:, 0].numpy() - nb).max() < 1e-13
+
+
+def test_boost_rest_frame():
+    """Lambda maps the fluid 4-velocity itself to (1, 0, 0, 0)."""
+    rng = np.random.default_rng(2)
+    for _ in range(5):
+        us = rng.normal(size=3)
+        u = np.concatenate([[math.sqrt(1 + us @ us)], us])
+        L = _boost_matrix(u)
+        assert np.abs(L @ u - np.array([1.0, 0, 0, 0])).max() < 1e-12
+
+
+# --------------------------------------------------------------------------
+# P4 / P5  closed-form attenuation and thermal relaxation
+# --------------------------------------------------------------------------
+def _uniform_problem(n, g, model, kappa, j=None, T=1.0, rho=1.0, kappa_s=0.0):
+    shape = (n, n, n)
+    wl = dict(n=shape, xlo=(0, 0, 0), xhi=(n, n, n), generation=g, weights="voronoi",
+              bc=("periodic",) * 3, model=model, gamma=5 / 3,
+              rho=np.full(shape, rho), T=np.full(shape, T), kappa_a=np.full(shape, kappa),
+              kappa_s=np.full(shape, kappa_s), j=None if j is None else np.full(shape, j),
+              u=None, I0_iso=np.zeros(shape))
+    return build_flat(wl)
+
+
+def test_exponential_attenuation_closed_form():
+    """j = 0, uniform alpha and I, periodic: transport of a uniform field is
+    zero, so the two-stage step gives I^(n) = I^0 (1 + alpha dt)^-n exactly."""
+    alpha, dt, I0 = 0.7, 0.4, 0.3
+    pb, I, T = _uniform_problem(4, 1, "fixed_emissivity", alpha, j=0.0)
+    I = torch.full_like(I, I0)
+    for k in range(1, 8):
+        I, T = st.step(pb, I, T, dt)
+        ref = I0 * (1 + alpha * dt) ** (-k)
+        assert torch.allclose(I, torch.full_like(I, ref), rtol=1e-14, atol=0)
+    # and the continuum decay exp(-alpha t) within the backward-Euler error
+    t = 7 * dt
+    assert abs(I.mean().item() - I0 * math.exp(-alpha * t)) < I0 * alpha * dt
+
+
+def test_thermal_relaxation_fixed_emissivity():
+    """j-bar = alpha B(T) at fixed T: I^(n) - B = (I^0 - B)(1 + alpha dt)^-n."""
+    alpha, dt, Tg = 1.3, 0.4, 1.5
+    B = Tg ** 4 / (4 * math.pi)
+    pb, I, T = _uniform_problem(4, 1, "fixed_emissivity", alpha, j=alpha * B, T=Tg)
+    I = torch.full_like(I, 0.05)
+    for k in range(1, 8):
+        I, T = st.step(pb, I, T, dt)
+        ref = B + (0.05 - B) * (1 + alpha * dt) ** (-k)
+        assert torch.allclose(I, torch.full_like(I, ref), rtol=1e-13, atol=1e-16)
+
+
+def test_equilibration_paper_setup():
+    """Sec. 4.11: T_gas = 2, T_rad = 1, rho = 1, Gamma = 5/3 in one isolated
+    cell relax to the T_eq fixed by T^4 + rho T/(Gamma-1) = u, and the total
+    energy is conserved at every step."""
+    ref = gold("equilibration.json")
+    gam, rho, Tg, Tr = ref["gamma"], ref["rho"], ref["T_gas"], ref["T_rad"]
+    u_tot = Tr ** 4 + rho * Tg / (gam - 1)
+    assert abs(rho * Tg / (gam - 1) - ref["u_gas"]) < 1e-12
+    roots = np.roots([1, 0, 0, rho / (gam - 1), -u_tot])
+    Teq = max(r.real for r in roots if abs(r.imag) < 1e-12 and r.real > 0)
+    pb, I, T = _uniform_problem(1, ref["generation"], "kirchhoff_const", 1.0, T=Tg, rho=rho)
+    pb.gamma = gam
+    I = torch.full_like(I, Tr ** 4 / (4 * math.pi))
+    g = pb.geo.grid
+    Y = rho / (gam - 1)
+    for _ in range(60):
+        I, T = st.step(pb, I, T, 0.4)
+        E = st.moments(I, g.n, g.w)[0]
+        assert abs((E + Y * T).item() - u_tot) < 1e-13 * u_tot
+    assert abs(T.item() - Teq) < 1e-10
+    assert abs(E.item() - Teq ** 4) < 1e-9
+
+
+# --------------------------------------------------------------------------
+# P6  conservation (flat, periodic)
+# --------------------------------------------------------------------------
+def test_conservation_transport_per_direction():
+    """Source off (density below the floor): sum over cells of I_s is conserved
+    for every direction; the fluxes telescope in a periodic box."""
+    g = GeodesicGrid(1)
+    n = (6, 5, 7)
+    I0 = torch.tensor(W.random_intensity(g.ns, n, 5), dtype=F64)
+    wl = dict(n=n, xlo=(0, 0, 0), xhi=n, generation=1, weights="voronoi", bc=("periodic",) * 3,
+              model="kirchhoff_const", gamma=5 / 3, rho=np.full(n, 1e-5), T=np.ones(n),
+              kappa_a=np.ones(n), kappa_s=np.zeros(n), j=None, u=None, I0_iso=np.zeros(n))
+    pb, _, T = build_flat(wl, grid=g)
+    I = I0.clone()
+    for _ in range(5):
+        I, T = st.step(pb, I, T, 0.4)
+    assert torch.allclose(I.sum((1, 2, 3)), I0.sum((1, 2, 3)), rtol=1e-13, atol=0)
+    assert not torch.allclose(I, I0)
+
+
+@pytest.mark.parametrize("model", ["kirchhoff_const", "brems"])
+def test_conservation_total_energy(model):
+    """Source on: sum over cells of (E + Y T) is conserved by every step."""
+    n = (6, 6, 6)
+    wl = W.brems_flat(n=n, generation=1, seed=11)
+    wl["model"] = model
+    wl["kappa_a"] = np.random.default_rng(3).uniform(0.1, 3.0, n)
+    wl["kappa_s"] = np.random.default_rng(4).uniform(0.0, 1.0, n)
+    pb, I, T = build_flat(wl)
+    I = torch.tensor(W.random_intensity(pb.geo.grid.ns, n, 6, 0.0, 0.1), dtype=F64)
+    g = pb.geo.grid
+    Y = pb.rho / (pb.gamma - 1)
+    tot0 = (st.moments(I, g.n, g.w)[0] + Y * T).sum().item()
+    for _ in range(4):
+        I, T = st.step(pb, I, T, 0.4)
+        tot = (st.moments(I, g.n, g.w)[0] + Y * T).sum().item()
+        assert abs(tot - tot0) < 1e-13 * abs(tot0)
+    assert sum(pb.failed) == 0
+
+
+def test_source_energy_balance_moving_fluid():
+    """Moving fluid: the fluid-frame energy of the updated intensity,
+    sum w (nbar^0)^2 I_out, equals Ebar_+ of the balance, and Ebar_- equals
+    the contraction u_a u_b R-hat^(ab) of the input moments (Eq. Ebar_calc
+    with dObar = w/(nbar^0)^2 and Ibar = I (nbar^0)^4)."""
+    g = GeodesicGrid(2)
+    rng = np.random.default_rng(9)
+    nc = 7
+    It = torch.tensor(rng.uniform(0.01, 1.0, (g.ns, nc)))
+    us = rng.normal(size=(3, nc)) * 0.5
+    u = torch.tensor(np.concatenate([np.sqrt(1 + (us ** 2).sum(0))[None], us]))
+    rho = torch.tensor(rng.uniform(0.5, 2.0, nc))
+    T0 = torch.tensor(rng.uniform(0.5, 2.0, nc))
+    n0 = torch.tensor(rng.uniform(1.0, 1.5, nc))
+    for model in (src.KIRCHHOFF_CONST, src.BREMS):
+        diag = {}
+        Io, To, failed = src.interact(It, T0, T0 * 1.1, rho, u, n0, torch.tensor(g.n), torch.tensor(g.w),
+                                      0.3, model, 5 / 3, torch.full((nc,), 0.8), torch.full((nc,), 0.4),
+                                      None, 1.0, 1.0, 5e-4, diag=diag)
+        assert not failed.any()
+        nb = diag["nb0"]
+        w = torch.tensor(g.w).reshape(-1, 1)
+        Eout = (w * nb * nb * Io).sum(0)
+        assert torch.allclose(Eout, diag["Ep"], rtol=1e-12)
+        R = st.moments(It, g.n, g.w)
+        ul = torch.stack([-u[0], u[1], u[2], u[3]])
+        Ec = sum(ul[a] * ul[b] * R[k] * (1 if a == b else 2) for k, (a, b) in enumerate(st.SYM10))
+        assert torch.allclose(diag["Em"], Ec, rtol=1e-13)
+        # energy exchanged with the gas
+        assert torch.allclose(diag["Ep"] + diag["Y"] * To, diag["Em"] + diag["Y"] * T0, rtol=1e-13)
+
+
+# --------------------------------------------------------------------------
+# P7  flux limits (Sec. 3.5, App. B)
+# --------------------------------------------------------------------------
+def _line(vals):
+    return torch.tensor(vals, dtype=F64).reshape(1, -1)
+
+
+def test_flux_vacuum_limit_is_upwind():
+    """tau = 0 reduces Eq. flux_Jiang to the vacuum flux of
+    Eq. spatial_fluxes_vacuum: n_0 n^a times the upwind reconstructed state.
+    On linear data the PLI states are exact, so the face value is known."""
+    a0, b0 = 0.3, 0.05
+    P = _line([a0 + b0 * k for k in range(10)])
+    n = 6
+    for nu in (0.8, -0.6, 0.0):
+        F = tr.face_fluxes(P, torch.tensor(nu, dtype=F64), torch.tensor(-1.0, dtype=F64),
+                           torch.tensor(1.0, dtype=F64), torch.zeros(n + 1, dtype=F64),
+                           torch.zeros(n + 1, dtype=F64), torch.zeros(n + 1, dtype=F64), tr.LIM_MC)
+        face_val = torch.tensor([a0 + b0 * (f + 1.5) for f in range(n + 1)], dtype=F64)
+        assert torch.allclose(F[0], -nu * face_val, rtol=1e-14, atol=1e-16)
+
+
+def test_flux_diffusion_limit():
+    """tau >> 1: the flux tends to the diffusion flux -|mu|/(2 tau) (I_l+1 - I_l)
+    of App. B (cut-off terms vanish, both speeds tend to |n|/tau)."""
+    rng = np.random.default_rng(3)
+    P = _line(rng.uniform(0, 1, 12))
+    n = 8
+    tau = torch.full((n + 1,), 700.0, dtype=F64)
+    for nu in (0.9, -0.4):
+        F = tr.face_fluxes(P, torch.tensor(nu, dtype=F64), torch.tensor(1.0, dtype=F64),
+                           torch.tensor(1.0, dtype=F64), tau, torch.zeros(n + 1, dtype=F64),
+                           torch.zeros(n + 1, dtype=F64), tr.LIM_MC)
+        dI = P[0, 2:n + 3] - P[0, 1:n + 2]
+        ref = -abs(nu) / (2 * 700.0) * dI
+        assert torch.allclose(F[0], ref, rtol=1e-13, atol=1e-18)
+
+
+def test_speed_factors_limits_and_continuity():
+    """f2 -> 1, f4 -> 0 as tau -> 0; both -> 1/tau as tau -> infinity; the
+    small-tau series joins the exact expression continuously."""
+    t = torch.tensor([0.0, 1e-12, 9.999e-5, 1.0001e-4, 0.5, 3.0, 50.0], dtype=F64)
+    f2, f4 = tr.speed_factors(t)
+    assert f2[0] == 1.0 and f4[0] == 0.0
+    ref2 = torch.tensor([math.sqrt(-math.expm1(-x * x)) / x if x > 0 else 1.0 for x in t.tolist()], dtype=F64)
+    ref4 = torch.tensor([math.sqrt(-math.expm1(-x ** 4)) / x if x > 0 else 0.0 for x in t.tolist()], dtype=F64)
+    assert torch.allclose(f2[1:], ref2[1:], rtol=1e-12)
+    assert torch.allclose(f4[2:], ref4[2:], rtol=1e-8)
+    assert abs(f2[-1].item() * 50 - 1) < 1e-15 and abs(f4[-1].item() * 50 - 1) < 1e-15
+
+
+def test_uniform_state_preserved_by_transport():
+    g = GeodesicGrid(1)
+    geo = FlatCartesian((5, 4, 6), (0, 0, 0), (5, 4, 6), g)
+    I = torch.full((g.ns, 5, 4, 6), 0.37, dtype=F64)
+    al = torch.tensor(np.random.default_rng(1).uniform(0, 5, (5, 4, 6)))
+    v = torch.zeros((3, 5, 4, 6), dtype=F64)
+    It = tr.transport(I, I, 0.4, 0.4, geo, al * 0 + 1.3, v, 1.0, (0,) * 3, (0,) * 3, tr.LIM_MC)
+    assert torch.allclose(It, I, rtol=1e-15, atol=0)
+
+
+def test_tau_uses_the_two_cells_adjacent_to_each_face():
+    """An opacity step: faces between two transparent cells carry the vacuum
+    flux, the face between a transparent and an opaque cell is cut off, so on
+    linear data the divergence is known in closed form on each side."""
+    g = GeodesicGrid(1)
+    n = (10, 1, 1)
+    geo = FlatCartesian(n, (0, 0, 0), n, g)
+    a0, b0 = 0.5, 0.03
+    x = torch.arange(n[0], dtype=F64)
+    I = (a0 + b0 * x).reshape(1, -1, 1, 1).expand(g.ns, -1, 1, 1).clone()
+    al = torch.zeros(n, dtype=F64)
+    al[5:] = 1e8
+    v = torch.zeros((3,) + n, dtype=F64)
+    div = tr.spatial_divergence(I, geo, al, v, 0.4, 1.0, (1,) * 3, (1,) * 3, tr.LIM_MC)
+    nx = torch.tensor(g.n[:, 0], dtype=F64)
+    # cells 2 and 3 (away from the outflow boundary): both faces transparent,
+    # div = n_0 n^x (dI/dx) = -n^x b0
+    for c in (2, 3):
+        assert torch.allclose(div[:, c, 0, 0], -nx * b0, rtol=1e-12, atol=1e-15)
+    # cell 4: lower face (3|4) transparent, upper face (4|5, tau = 2e7) cut off
+    lower = -nx * (a0 + b0 * 3.5)
+    assert torch.allclose(div[:, 4, 0, 0], -lower, rtol=0, atol=1e-8)
+    # cells 5..8: both faces opaque -> fluxes ~ 1/tau, divergence ~ 0
+    assert div[:, 5:9].abs().max() < 1e-8
+
+
+def test_zero_incoming_side_selection():
+    """Zero-incoming at the lower x face: directions entering the box (n^x > 0)
+    lose intensity in the first cell, leaving directions (n^x < 0) do not."""
+    g = GeodesicGrid(1)
+    n = (6, 2, 2)
+    geo = FlatCartesian(n, (0, 0, 0), n, g)
+    I = torch.ones((g.ns,) + n, dtype=F64)
+    al = torch.zeros(n, dtype=F64)
+    v = torch.zeros((3,) + n, dtype=F64)
+    It = tr.transport(I, I, 0.2, 0.4, geo, al, v, 1.0, (2, 0, 0), (1, 0, 0), tr.LIM_MC)
+    nx = torch.tensor(g.n[:, 0], dtype=F64)
+    first = It[:, 0, 0, 0]
+    assert (first[nx > 1e-6] < 1 - 1e-3).all()
+    assert torch.allclose(first[nx <= 0], torch.ones_like(first[nx <= 0]), rtol=1e-15)
+    # the upper x face is outflow: nothing changes at the last cell
+    assert torch.allclose(It[:, -1], torch.ones_like(It[:, -1]), rtol=1e-15)
+
+
+def test_predictor_corrector_is_second_order():
+    """Sec. 3.7 two-stage step: smooth free streaming along n = (0,0,1)
+    converges at about second order in dx at fixed CFL (a wrong stage length
+    or a missing corrector drops the order to one or destabilises)."""
+    g = GeodesicGrid(0)
+    errs = []
+    for nz in (32, 64, 128):
+        n = (1, 1, nz)
+        L = 1.0
+        dx = L / nz
+        z = (np.arange(nz) + 0.5) * dx
+        prof = lambda zz: np.exp(-((((zz - 0.3) % 1.0) - 0.5) / 0.12) ** 2)
+        I = torch.zeros((g.ns,) + n, dtype=F64)
+        I[0, 0, 0, :] = torch.tensor(prof(z + 0.2))
+        wl = dict(n=n, xlo=(0, 0, 0), xhi=(1, 1, L), generation=0, weights="voronoi",
+                  bc=("periodic",) * 3, model="kirchhoff_const", gamma=5 / 3, rho=np.full(n, 1e-6),
+                  T=np.ones(n), kappa_a=np.zeros(n), kappa_s=np.zeros(n), j=None, u=None,
+                  I0_iso=np.zeros(n))
+        pb, _, T = build_flat(wl, grid=g)
+        dt = 0.4 * dx
+        nsteps = int(round(0.25 / dt))
+        for _ in range(nsteps):
+            I, T = st.step(pb, I, T, dt)
+        exact = prof(z + 0.2 - nsteps * dt)
+        errs.append(np.abs(I[0, 0, 0].numpy() - exact).sum() * dx)
+    order = [math.log2(errs[k] / errs[k + 1]) for k in range(2)]
+    assert min(order) > 1.6, (errs, order)
+
+
+def test_mc_limiter_textbook():
+    """MC limiter: central slope for smooth data, zero at extrema, twice the
+    one-sided slope near steep jumps."""
+    p = torch.tensor([1.0, 1.0, -1.0, 0.1, 3.0], dtype=F64)
+    q = torch.tensor([1.0, -1.0, -3.0, 3.0, 0.1], dtype=F64)
+    out = tr.limited_slope(p, q, tr.LIM_MC)
+    assert out.tolist() == [1.0, 0.0, -2.0, 0.2, 0.2]
+
+
+def test_zero_incoming_boundary_lets_beam_leave():
+    """Zero-incoming boundaries: a field streaming in vacuum leaves the box and
+    nothing enters; total energy never increases."""
+    g = GeodesicGrid(1)
+    n = (8, 8, 8)
+    wl = dict(n=n, xlo=(0, 0, 0), xhi=n, generation=1, weights="voronoi", bc=("zero_incoming",) * 3,
+              model="kirchhoff_const", gamma=5 / 3, rho=np.full(n, 1e-6), T=np.ones(n),
+              kappa_a=np.zeros(n), kappa_s=np.zeros(n), j=None, u=None, I0_iso=np.ones(n))
+    pb, I, T = build_flat(wl, grid=g)
+    last = st.moments(I, g.n, g.w)[0].sum().item()
+    for _ in range(30):
+        I, T = st.step(pb, I, T, 0.4)
+        e = st.moments(I, g.n, g.w)[0].sum().item()
+        assert e <= last * (1 + 1e-14)
+        last = e
+    assert last < 0.1 * 4 * math.pi * 512
+
+
+# --------------------------------------------------------------------------
+# P8  free streaming (Sec. 4.1 idea: fronts move at the speed of light)
+# --------------------------------------------------------------------------
+def test_vacuum_advection_speed():
+    """A smooth bump carried by the pole direction n = (0,0,1) in vacuum moves
+    with speed n^3 = 1: its centroid advances by t."""
+    g = GeodesicGrid(1)
+    assert np.allclose(g.n[0], [0, 0, 1])
+    nz = 64
+    n = (1, 1, nz)
+    z = np.arange(nz) + 0.5
+    bump = np.exp(-((z - 20.0) / 4.0) ** 2)
+    I = torch.zeros((g.ns,) + n, dtype=F64)
+    I[0, 0, 0, :] = torch.tensor(bump)
+    wl = dict(n=n, xlo=(0, 0, 0), xhi=n, generation=1, weights="voronoi", bc=("periodic",) * 3,
+              model="kirchhoff_const", gamma=5 / 3, rho=np.full(n, 1e-6), T=np.ones(n),
+              kappa_a=np.zeros(n), kappa_s=np.zeros(n), j=None, u=None, I0_iso=np.zeros(n))
+    pb, _, T = build_flat(wl, grid=g)
+    dt = 0.4
+    for _ in range(50):
+        I, T = st.step(pb, I, T, dt)
+    prof = I[0, 0, 0].numpy()
+    c = (prof * z).sum() / prof.sum()
+    assert abs(c - (20.0 + 50 * dt)) < 0.05
+    assert prof.min() > -1e-6 and prof.max() <= 1.0
+
+
+# --------------------------------------------------------------------------
+# P10  temperature equations (Sec. 3.6.2)
+# --------------------------------------------------------------------------
+def test_newton_matches_closed_form_method2():
+    """Method 2 (Eq. implicit_T) is a quadratic in y = sqrt(T): Newton's root
+    equals the closed form y = -2K / (b + sqrt(b^2 - 4 a K))."""
+    rng = np.random.default_rng(5)
+    a = torch.tensor(rng.uniform(0.1, 10, 200))
+    b = torch.tensor(rng.uniform(1e-3, 10, 200))
+    K = -torch.tensor(rng.uniform(1e-3, 100, 200))
+    y, ok = src.newton_positive_root(a, b, K, 2.0)
+    ref = -2 * K / (b + torch.sqrt(b * b - 4 * a * K))
+    assert ok.all()
+    assert torch.allclose(y, ref, rtol=1e-14)
+
+
+def test_newton_quartic_root_is_unique_positive():
+    """Method 1 quartic (Eq. semi_implicit_T): the root is the unique positive
+    real root given by numpy's companion-matrix solver."""
+    rng = np.random.default_rng(6)
+    for _ in range(50):
+        a, b, K = rng.uniform(1e-3, 5), rng.uniform(1e-3, 5), -rng.uniform(1e-3, 50)
+        T, ok = src.newton_positive_root(torch.tensor([a], dtype=F64), torch.tensor([b], dtype=F64), torch.tensor([K], dtype=F64), 4.0)
+        r = [x.real for x in np.roots([a, 0, 0, b, K]) if abs(x.imag) < 1e-9 and x.real > 0]
+        assert ok.all() and len(r) == 1
+        assert abs(T.item() - r[0]) < 1e-12 * r[0]
+
+
+# --------------------------------------------------------------------------
+# P11  moments (Eq. R)
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("g", [1, 2, 3])
+def test_isotropic_moments(g):
+    G = GeodesicGrid(g)
+    I = torch.full((G.ns, 2, 1, 1), 0.25, dtype=F64)
+    R = st.moments(I, G.n, G.w)[:, 0, 0, 0]
+    ref = torch.zeros(10, dtype=F64)
+    ref[0] = 4 * math.pi * 0.25
+    for k in (4, 7, 9):
+        ref[k] = 4 * math.pi / 3 * 0.25
+    assert torch.allclose(R, ref, atol=1e-14)
+
+
+def test_moments_match_direct_sum():
+    """Moments of a single-direction beam are w_s n^a n^b I."""
+    G = GeodesicGrid(2)
+    I = torch.zeros((G.ns, 1, 1, 1), dtype=F64)
+    s = 17
+    I[s] = 2.0
+    R = st.moments(I, G.n, G.w)[:, 0, 0, 0]
+    n4 = np.concatenate([[1.0], G.n[s]])
+    for k, (a, b) in enumerate(st.SYM10):
+        assert abs(R[k].item() - G.w[s] * n4[a] * n4[b] * 2.0) < 1e-15
+
+
+def test_force_at_rest_equals_gas_heating():
+    """G^0 dt = Y (T^(n+1) - T^n) for a fluid at rest (Sec. 3.6.3, conservative
+    4-force from the change of R^(0a) in the interaction step)."""
+    n = (4, 4, 4)
+    wl = W.brems_flat(n=n, generation=1, seed=3)
+    pb, I, T = build_flat(wl)
+    I = torch.tensor(W.random_intensity(pb.geo.grid.ns, n, 7, 0.0, 0.2), dtype=F64)
+    In, Tn, G = st.step(pb, I, T, 0.4, want_G=True)
+    Y = pb.rho / (pb.gamma - 1)
+    assert torch.allclose(G[0] * 0.4, Y * (Tn - T), rtol=1e-12, atol=1e-14)
