@@ -1,0 +1,209 @@
+"""Throughput of the gray transfer step on one MI355X.
+
+One benchmark step is one pass of the whole hot path over the workload:
+rt_step (two transport stages, two implicit interactions) followed by
+rt_moments (R^(ab) of the new intensity).  Workload: flat 128^3 cells x 162
+directions (geodesic generation 2), lognormal density (sigma_ln = 1, k^-2
+random field), T ~ U[0.5, 2], alpha^a = rho^2 T^-3.5, alpha^s = rho, Method 2,
+periodic, dt = 0.4; synthetic inputs from `workloads`, resident in HBM before
+the timed region.  The FP32 transport form is the headline value; the plain
+FP64 form runs the same workload and its rate is reported beside it.
+
+Prints one JSON line.  Usage: python bench.py [--steps K] [--warmup W] [--gpus 1]
+"""
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X published HBM3E bandwidth
+KERNEL_SRC = os.path.join(ROOT, "paper_2508_15532_amd", "csrc", "kernels.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+
+
+def algorithmic_bytes(kind, elem, ns, nc, moving=False):
+    """Bytes a launch of each kernel must move at minimum (its inputs read once
+    and outputs written once), per launch over the whole grid."""
+    cd = ns * nc
+    cell_face = 3 * 5 * elem          # one set of face coefficients per cell and axis
+    if kind == "transport1":          # read I^n, write I~
+        return 2 * elem * cd + cell_face * nc
+    if kind == "transport2":          # read I*, read I^n, write I~
+        return 3 * elem * cd + cell_face * nc
+    if kind == "source1":             # read I~, write I*; T, rho, abar_a, abar_s, write T*
+        return 2 * elem * cd + 5 * 8 * nc
+    if kind == "source2":             # read I~, write I^n+1; T, T*, rho, abar_a, abar_s, write T
+        return 2 * elem * cd + 6 * 8 * nc
+    if kind == "moments":             # read I, write 10 components
+        return elem * cd + 80 * nc
+    raise KeyError(kind)
+
+
+def step_algorithmic_bytes(elem, ns, nc):
+    """Per step, what the method itself must move: stage 1 reads I^n and writes
+    I*, stage 2 reads I* and I^n and writes I^(n+1) (5 intensity transfers per
+    cell-direction), plus R (80 B per cell)."""
+    return 5 * elem * ns * nc + 80 * nc
+
+
+def make_inputs(wl, ctx, torch):
+    dev = torch.device("cuda", 0)
+    rho = torch.as_tensor(wl["rho"], dtype=torch.float64).reshape(-1).to(dev)
+    T = torch.as_tensor(wl["T"], dtype=torch.float64).reshape(-1).to(dev)
+    ctx.set_opacities(wl["model"], rho, gamma=wl["gamma"], C_a=wl["C_a"], C_s=wl["C_s"])
+    I = (T ** 4 / (4 * math.pi)).reshape(1, -1).expand(ctx.ns, -1).to(ctx.intensity_dtype).contiguous()
+    R = torch.empty((10, ctx.nc), dtype=torch.float64, device=dev)
+    return rho, I, T, R
+
+
+def run_form(wl, precision, steps, warmup, torch, P):
+    ctx = P.RTContext(wl["n"], wl["xlo"], wl["xhi"], wl["generation"], weights=wl["weights"],
+                      precision=precision, bc=wl["bc"])
+    ctx.set_metric("flat", cfl=0.4)
+    rho, I, T, R = make_inputs(wl, ctx, torch)
+    dt = wl["dt"]
+    for _ in range(warmup):
+        ctx.step(I, T, dt, 1)
+        ctx.moments(I, R)
+    torch.cuda.synchronize()
+    ctx.set_debug(2)                      # HIP events around every launch
+    ctx.kernel_times()                    # reset the tally
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ctx.step(I, T, dt, 1)
+        ctx.moments(I, R)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ktimes = ctx.kernel_times()
+    ctx.set_debug(0)
+    ok = bool(torch.isfinite(R).all().item())
+    ns, nc = ctx.ns, ctx.nc
+    ctx.close()
+    del I, T, R, rho
+    torch.cuda.empty_cache()
+    return dict(wall=wall, ktimes=ktimes, ns=ns, nc=nc, finite=ok,
+                elem=4 if precision == "fp32" else 8)
+
+
+def traffic_for(kernel, elem):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary, if it was taken on the current kernel source; else None."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            rec = json.load(f)
+        src = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+        if rec.get("kernels_sha256") != src:
+            return None
+        return rec["per_launch_bytes"].get(f"{kernel}_{'fp32' if elem == 4 else 'fp64'}")
+    except (OSError, KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(torch):
+    """The FP64 oracle, as it stands, on a bounded sample of the same workload:
+    a periodic 64^3 sub-box x 162 directions, two steps (about 10-30 s)."""
+    import workloads as W
+    from oracle import step as st
+    from oracle.setup import build_flat
+    n, nsteps = 64, 2
+    wl = W.brems_flat(n=n)
+    pb, I, T = build_flat(wl)
+    t0 = time.perf_counter()
+    for _ in range(nsteps):
+        I, T = st.step(pb, I, T, wl["dt"])
+        R = st.moments(I, pb.geo.grid.n, pb.geo.grid.w)
+    dt = time.perf_counter() - t0
+    assert bool(torch.isfinite(R).all())
+    cd = pb.geo.grid.ns * n ** 3 * nsteps
+    return {"value": cd / dt, "unit": "cell-direction updates/s", "cores": torch.get_num_threads(),
+            "kind": "oracle",
+            "sample": f"{nsteps} steps (rt_step + moments) of a periodic {n}^3 x {pb.geo.grid.ns} "
+                      f"box drawn with the 128^3 workload's recipe ({dt:.1f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--forms", default="fp32,fp64")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU "
+              "decomposition is designed but not built", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import workloads as W
+    import paper_2508_15532_amd as P
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    wl = W.brems_flat()
+    forms = args.forms.split(",")
+    res = {}
+    for prec in forms:
+        print(f"bench: {prec} 128^3 x 162, {args.warmup} warmup + {args.steps} timed steps",
+              file=sys.stderr, flush=True)
+        res[prec] = run_form(wl, prec, args.steps, args.warmup, torch, P)
+    head = "fp32" if "fp32" in res else forms[0]
+    r = res[head]
+    cd_per_step = r["ns"] * r["nc"]
+    value = cd_per_step * args.steps / r["wall"]
+    ms_per_step = 1e3 * r["wall"] / args.steps
+    # roofline of the dominant kernel, from HIP events over the timed region
+    kt = {k: v for k, v in r["ktimes"].items() if v[0] > 0 and k not in ("opacity", "faces")}
+    dom = max(kt, key=lambda k: kt[k][1])
+    launches, tot_ms = kt[dom]
+    avg_s = tot_ms / launches / 1e3
+    abytes = algorithmic_bytes(dom, r["elem"], r["ns"], r["nc"])
+    achieved = abytes / avg_s / 1e9
+    traffic = traffic_for(dom, r["elem"])
+    step_bytes = step_algorithmic_bytes(r["elem"], r["ns"], r["nc"])
+    out = {
+        "metric": "cell-direction updates/s for rt_step (FP32 vs FP64) + % HBM roofline",
+        "value": value,
+        "unit": "cell-direction updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if head == "fp32" else "f64",
+        "data": "synthetic",
+        "config": {"workload": "flat 128^3 x 162 directions (geodesic g2), lognormal rho, "
+                               "T~U[0.5,2], alpha^a=rho^2 T^-3.5, alpha^s=rho, Method 2, periodic",
+                   "form": "fp32 transport + fp64 interaction/moments" if head == "fp32" else "fp64",
+                   "cells": r["nc"], "directions": r["ns"], "step": "rt_step + rt_moments",
+                   "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": dom,
+                     "kernel_avg_ms": avg_s * 1e3,
+                     "step_frac": step_bytes * args.steps / r["wall"] / 1e9 / HBM_PEAK_GBS},
+        "kernels_ms_per_step": {k: v[1] / args.steps for k, v in r["ktimes"].items() if v[0]},
+    }
+    for prec, rr in res.items():
+        out[f"value_{prec}"] = rr["ns"] * rr["nc"] * args.steps / rr["wall"]
+        out[f"ms_per_step_{prec}"] = 1e3 * rr["wall"] / args.steps
+        if not rr["finite"]:
+            out["error"] = f"non-finite moments in the {prec} run"
+    if "fp32" in res and "fp64" in res:
+        out["speedup_fp32_over_fp64"] = out["value_fp32"] / out["value_fp64"]
+    if not args.no_cpu_baseline:
+        print("bench: CPU oracle baseline", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(torch)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

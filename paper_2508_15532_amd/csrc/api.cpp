@@ -1,0 +1,448 @@
+// C ABI of the library (declared in include/rt.h): argument checking, context
+// and device-memory management, and the order of kernel launches of a step.
+#include <hip/hip_runtime_api.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <exception>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "ctx.hpp"
+
+namespace rt {
+namespace {
+thread_local std::string g_err;
+}
+
+void set_error(const std::string& msg) { g_err = msg; }
+
+namespace {
+
+rt_status fail(rt_status s, const std::string& msg) {
+  set_error(msg);
+  return s;
+}
+
+rt_status hip_fail(hipError_t e, const char* what) {
+  return fail(RT_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define RT_HIP(call)                                        \
+  do {                                                      \
+    hipError_t e_ = (call);                                 \
+    if (e_ != hipSuccess) return hip_fail(e_, #call);       \
+  } while (0)
+
+template <typename T>
+rt_status alloc(T** p, size_t bytes) {
+  if (*p) return RT_OK;
+  hipError_t e = hipMalloc((void**)p, bytes);
+  if (e != hipSuccess) {
+    *p = nullptr;
+    (void)hipGetLastError();
+    return fail(RT_E_NOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed: " +
+                                hipGetErrorString(e));
+  }
+  return RT_OK;
+}
+
+template <typename T>
+void release(T*& p) {
+  if (p) (void)hipFree((void*)p);
+  p = nullptr;
+}
+
+bool aligned(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 255u) == 0; }
+
+rt_status use_device(const rt_ctx* c) {
+  int cur = -1;
+  RT_HIP(hipGetDevice(&cur));
+  if (cur != c->device) RT_HIP(hipSetDevice(c->device));
+  return RT_OK;
+}
+
+hipEvent_t take_event(rt_ctx* c) {
+  if (!c->event_pool.empty()) {
+    hipEvent_t e = c->event_pool.back();
+    c->event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Enqueue one launch; with timing on, bracket it with events on the same stream.
+template <typename F>
+hipError_t timed(rt_ctx* c, int kind, hipStream_t st, F&& launch) {
+  if (!(c->debug & 2)) return launch();
+  hipEvent_t a = take_event(c), b = take_event(c);
+  if (!a || !b) return hipErrorOutOfMemory;
+  hipError_t e = hipEventRecord(a, st);
+  if (e != hipSuccess) return e;
+  e = launch();
+  if (e != hipSuccess) return e;
+  e = hipEventRecord(b, st);
+  if (e != hipSuccess) return e;
+  c->timed.push_back({kind, a, b});
+  return hipSuccess;
+}
+
+}  // namespace
+}  // namespace rt
+
+using namespace rt;
+
+extern "C" {
+
+const char* rt_last_error(void) { return rt::g_err.c_str(); }
+
+rt_status rt_init_grid(const rt_grid_desc* d, rt_ctx** out) {
+  if (!out) return fail(RT_E_ARG, "rt_init_grid: out is NULL");
+  *out = nullptr;
+  if (!d) return fail(RT_E_ARG, "rt_init_grid: descriptor is NULL");
+  for (int a = 0; a < 3; ++a) {
+    if (d->n[a] < 1) return fail(RT_E_ARG, "rt_init_grid: n[a] must be >= 1");
+    if (!(d->xhi[a] > d->xlo[a])) return fail(RT_E_ARG, "rt_init_grid: xhi must exceed xlo");
+    for (int side = 0; side < 2; ++side) {
+      int b = side ? d->bc_hi[a] : d->bc_lo[a];
+      if (b < RT_BC_PERIODIC || b > RT_BC_ZERO_INCOMING) return fail(RT_E_ARG, "rt_init_grid: bad bc");
+    }
+    if ((d->bc_lo[a] == RT_BC_PERIODIC) != (d->bc_hi[a] == RT_BC_PERIODIC))
+      return fail(RT_E_ARG, "rt_init_grid: periodic must be set on both sides of an axis");
+  }
+  if (d->coords != RT_CART) return fail(RT_E_ARG, "rt_init_grid: only RT_CART coordinates are built");
+  if (d->generation < 0 || d->generation > 5) return fail(RT_E_ARG, "rt_init_grid: generation in 0..5");
+  if (d->weights != RT_W_VORONOI && d->weights != RT_W_EQUAL) return fail(RT_E_ARG, "rt_init_grid: bad weights");
+  if (d->precision != RT_FP64 && d->precision != RT_FP32_TRANSPORT)
+    return fail(RT_E_ARG, "rt_init_grid: bad precision");
+  if (d->limiter != RT_LIM_MC && d->limiter != RT_LIM_MINMOD) return fail(RT_E_ARG, "rt_init_grid: bad limiter");
+  if (!(d->abar >= 0.0) || !(d->rho_floor >= 0.0)) return fail(RT_E_ARG, "rt_init_grid: abar, rho_floor >= 0");
+  long long nc = (long long)d->n[0] * d->n[1] * d->n[2];
+  if (nc > (1ll << 40)) return fail(RT_E_ARG, "rt_init_grid: too many cells");
+
+  rt_ctx* c = nullptr;
+  try {
+    c = new rt_ctx();
+    c->grid = build_geodesic_grid(d->generation, d->weights == RT_W_EQUAL);
+  } catch (const std::bad_alloc&) {
+    delete c;
+    return fail(RT_E_NOMEM, "rt_init_grid: host allocation failed");
+  } catch (const std::exception& e) {
+    delete c;
+    return fail(RT_E_ARG, std::string("rt_init_grid: ") + e.what());
+  }
+  c->desc = *d;
+  c->ns = c->grid.ns;
+  for (int a = 0; a < 3; ++a) {
+    c->n[a] = d->n[a];
+    c->dx[a] = (d->xhi[a] - d->xlo[a]) / d->n[a];
+  }
+  c->nc = nc;
+  c->fp32 = d->precision == RT_FP32_TRANSPORT;
+  c->elem = c->fp32 ? 4 : 8;
+  hipError_t e = hipGetDevice(&c->device);
+  if (e != hipSuccess) {
+    delete c;
+    return hip_fail(e, "hipGetDevice");
+  }
+  const int ns = c->ns;
+  const int ns4 = (ns + 3) / 4 * 4;
+  std::vector<double> dir(3 * ns), w(ns), W16((size_t)ns4 * 16, 0.0);
+  std::vector<float> dirf(3 * ns);
+  for (int s = 0; s < ns; ++s) {
+    for (int k = 0; k < 3; ++k) {
+      dir[k * ns + s] = c->grid.dir[s][k];
+      dirf[k * ns + s] = (float)c->grid.dir[s][k];
+    }
+    w[s] = c->grid.w[s];
+    double n4[4] = {1.0, c->grid.dir[s][0], c->grid.dir[s][1], c->grid.dir[s][2]};
+    static const int pa[10] = {0, 0, 0, 0, 1, 1, 1, 2, 2, 3};
+    static const int pb[10] = {0, 1, 2, 3, 1, 2, 3, 2, 3, 3};
+    for (int k = 0; k < 10; ++k) W16[(size_t)s * 16 + k] = w[s] * n4[pa[k]] * n4[pb[k]];
+  }
+  rt_status st = RT_OK;
+  if ((st = alloc(&c->d_dir, dir.size() * 8)) || (st = alloc(&c->d_dir_f, dirf.size() * 4)) ||
+      (st = alloc(&c->d_w, w.size() * 8)) || (st = alloc(&c->d_W16, W16.size() * 8)) ||
+      (st = alloc(&c->d_count, 2 * sizeof(unsigned long long)))) {
+    rt_destroy(c);
+    return st;
+  }
+  if ((e = hipMemcpy(c->d_dir, dir.data(), dir.size() * 8, hipMemcpyHostToDevice)) != hipSuccess ||
+      (e = hipMemcpy(c->d_dir_f, dirf.data(), dirf.size() * 4, hipMemcpyHostToDevice)) != hipSuccess ||
+      (e = hipMemcpy(c->d_w, w.data(), w.size() * 8, hipMemcpyHostToDevice)) != hipSuccess ||
+      (e = hipMemcpy(c->d_W16, W16.data(), W16.size() * 8, hipMemcpyHostToDevice)) != hipSuccess ||
+      (e = hipMemset(c->d_count, 0, 2 * sizeof(unsigned long long))) != hipSuccess) {
+    rt_destroy(c);
+    return hip_fail(e, "rt_init_grid upload");
+  }
+  *out = c;
+  return RT_OK;
+}
+
+rt_status rt_geodesic_grid(int generation, int weights, int* n_dirs, double* dirs_host,
+                           double* w_host, double* area_host) {
+  if (generation < 0 || generation > 5) return fail(RT_E_ARG, "rt_geodesic_grid: generation in 0..5");
+  if (weights != RT_W_VORONOI && weights != RT_W_EQUAL) return fail(RT_E_ARG, "rt_geodesic_grid: bad weights");
+  GeodesicGrid G;
+  try {
+    G = build_geodesic_grid(generation, weights == RT_W_EQUAL);
+  } catch (const std::exception& e) {
+    return fail(RT_E_NOMEM, std::string("rt_geodesic_grid: ") + e.what());
+  }
+  if (n_dirs) *n_dirs = G.ns;
+  for (int s = 0; s < G.ns; ++s) {
+    if (dirs_host)
+      for (int k = 0; k < 3; ++k) dirs_host[3 * s + k] = G.dir[s][k];
+    if (w_host) w_host[s] = G.w[s];
+    if (area_host) area_host[s] = G.area[s];
+  }
+  return RT_OK;
+}
+
+rt_status rt_grid_info(const rt_ctx* c, int* n_dirs, double* dirs_host, double* w_host,
+                       double* area_host) {
+  if (!c) return fail(RT_E_ARG, "rt_grid_info: ctx is NULL");
+  if (n_dirs) *n_dirs = c->ns;
+  for (int s = 0; s < c->ns; ++s) {
+    if (dirs_host)
+      for (int k = 0; k < 3; ++k) dirs_host[3 * s + k] = c->grid.dir[s][k];
+    if (w_host) w_host[s] = c->grid.w[s];
+    if (area_host) area_host[s] = c->grid.area[s];
+  }
+  return RT_OK;
+}
+
+rt_status rt_set_metric(rt_ctx* c, int kind, double M, double a, double cfl, double* dt_max_out) {
+  (void)M;
+  (void)a;
+  if (!c) return fail(RT_E_ARG, "rt_set_metric: ctx is NULL");
+  if (!(cfl > 0.0)) return fail(RT_E_ARG, "rt_set_metric: cfl must be > 0");
+  if (kind != RT_FLAT) return fail(RT_E_ARG, "rt_set_metric: only RT_FLAT is built for RT_CART");
+  rt_status st = use_device(c);
+  if (st) return st;
+  c->metric_kind = kind;
+  double vmax[3] = {0, 0, 0};
+  for (int s = 0; s < c->ns; ++s)
+    for (int k = 0; k < 3; ++k) vmax[k] = std::max(vmax[k], std::fabs(c->grid.dir[s][k]));
+  double dtm = INFINITY;
+  for (int k = 0; k < 3; ++k) dtm = std::min(dtm, c->dx[k] / vmax[k]);
+  c->dt_max = cfl * dtm;
+  // per-stage scratch
+  const size_t nc = (size_t)c->nc, ns = (size_t)c->ns;
+  const size_t fel = c->fp32 ? 4 : 8;
+  c->nface[0] = (long long)(c->n[0] + 1) * c->n[1] * c->n[2];
+  c->nface[1] = (long long)c->n[0] * (c->n[1] + 1) * c->n[2];
+  c->nface[2] = (long long)c->n[0] * c->n[1] * (c->n[2] + 1);
+  if ((st = alloc(&c->d_abar_a, nc * 8)) || (st = alloc(&c->d_abar_s, nc * 8)) ||
+      (st = alloc(&c->d_ahat, nc * 8)) || (st = alloc(&c->d_Tstar, nc * 8)) ||
+      (st = alloc(&c->d_face[0], 5 * c->nface[0] * fel)) ||
+      (st = alloc(&c->d_face[1], 5 * c->nface[1] * fel)) ||
+      (st = alloc(&c->d_face[2], 5 * c->nface[2] * fel)) ||
+      (st = alloc(&c->d_Itil, ns * nc * c->elem)) || (st = alloc(&c->d_Istar, ns * nc * c->elem)))
+    return st;
+  c->metric_set = true;
+  if (dt_max_out) *dt_max_out = c->dt_max;
+  return RT_OK;
+}
+
+rt_status rt_set_opacities(rt_ctx* c, const rt_opacity_desc* o, hipStream_t stream) {
+  if (!c || !o) return fail(RT_E_ARG, "rt_set_opacities: NULL argument");
+  if (!c->metric_set) return fail(RT_E_STATE, "rt_set_opacities: call rt_set_metric first");
+  if (o->model < RT_OPAC_KIRCHHOFF_CONST || o->model > RT_OPAC_FIXED_EMISSIVITY)
+    return fail(RT_E_ARG, "rt_set_opacities: bad model");
+  if (!(o->gamma > 1.0)) return fail(RT_E_ARG, "rt_set_opacities: gamma must be > 1");
+  if (!o->rho) return fail(RT_E_ARG, "rt_set_opacities: rho is required");
+  if (o->newton_max_iter < 1 || !(o->newton_rtol > 0.0))
+    return fail(RT_E_ARG, "rt_set_opacities: newton_max_iter >= 1 and newton_rtol > 0");
+  const void* ptrs[] = {o->rho, o->u, o->kappa_a, o->kappa_s, o->j};
+  for (const void* p : ptrs)
+    if (p && !aligned(p)) return fail(RT_E_ARG, "rt_set_opacities: arrays must be 256-byte aligned");
+  rt_status st = use_device(c);
+  if (st) return st;
+  const size_t nb = (size_t)c->nc * 8;
+  if ((st = alloc(&c->d_rho, nb)) || (st = alloc(&c->d_uhat, 4 * nb)) || (st = alloc(&c->d_v, 3 * nb)))
+    return st;
+  RT_HIP(hipMemcpyAsync(c->d_rho, o->rho, nb, hipMemcpyDeviceToDevice, stream));
+  // flat metric, identity tetrad: u-hat = u; v^a = u^a / u^0 for the advection term
+  c->moving = o->u != nullptr;
+  RT_HIP(launch_fluid(c, o->u, stream));
+  auto copy_opt = [&](double** dst, const double* src) -> rt_status {
+    if (!src) {
+      release(*dst);
+      return RT_OK;
+    }
+    rt_status s2 = alloc(dst, nb);
+    if (s2) return s2;
+    RT_HIP(hipMemcpyAsync(*dst, src, nb, hipMemcpyDeviceToDevice, stream));
+    return RT_OK;
+  };
+  if ((st = copy_opt(&c->d_ka, o->kappa_a)) || (st = copy_opt(&c->d_ks, o->kappa_s)) ||
+      (st = copy_opt(&c->d_j, o->j)))
+    return st;
+  c->opac = *o;
+  c->opac.rho = c->opac.u = c->opac.kappa_a = c->opac.kappa_s = c->opac.j = nullptr;
+  c->opac_set = true;
+  return RT_OK;
+}
+
+rt_status rt_step(rt_ctx* c, void* I, double* T, double dt, int nsteps, double* G_out,
+                  hipStream_t stream) {
+  if (!c) return fail(RT_E_ARG, "rt_step: ctx is NULL");
+  if (!c->metric_set || !c->opac_set) return fail(RT_E_STATE, "rt_step: set metric and opacities first");
+  if (!I || !T) return fail(RT_E_ARG, "rt_step: I and T are required");
+  if (!aligned(I) || !aligned(T) || (G_out && !aligned(G_out)))
+    return fail(RT_E_ARG, "rt_step: arrays must be 256-byte aligned");
+  if (nsteps < 0) return fail(RT_E_ARG, "rt_step: nsteps must be >= 0");
+  if (!(dt > 0.0) || dt > c->dt_max * (1.0 + 1e-12))
+    return fail(RT_E_ARG, "rt_step: need 0 < dt <= dt_max (" + std::to_string(c->dt_max) + ")");
+  rt_status st = use_device(c);
+  if (st) return st;
+  for (int k = 0; k < nsteps; ++k) {
+    bool last = k == nsteps - 1;
+    // stage 1: fluxes of I^n, half step, interaction from T^n with opacities at T^n
+    RT_HIP(timed(c, RT_K_OPACITY, stream, [&] { return launch_opacity(c, T, stream); }));
+    RT_HIP(timed(c, RT_K_FACES, stream, [&] { return launch_faces(c, dt, stream); }));
+    RT_HIP(timed(c, RT_K_TRANSPORT1, stream,
+                 [&] { return launch_transport(c, I, I, c->d_Itil, 0.5 * dt, stream); }));
+    RT_HIP(timed(c, RT_K_SOURCE1, stream, [&] {
+      return launch_source(c, c->d_Itil, c->d_Istar, T, T, c->d_Tstar, 0.5 * dt, nullptr, stream);
+    }));
+    // stage 2: fluxes of I*, full step from I^n, energy balance from T^n, opacities at T*
+    RT_HIP(timed(c, RT_K_OPACITY, stream, [&] { return launch_opacity(c, c->d_Tstar, stream); }));
+    RT_HIP(timed(c, RT_K_FACES, stream, [&] { return launch_faces(c, dt, stream); }));
+    RT_HIP(timed(c, RT_K_TRANSPORT2, stream,
+                 [&] { return launch_transport(c, c->d_Istar, I, c->d_Itil, dt, stream); }));
+    RT_HIP(timed(c, RT_K_SOURCE2, stream, [&] {
+      return launch_source(c, c->d_Itil, I, T, c->d_Tstar, T, dt, last ? G_out : nullptr, stream);
+    }));
+  }
+  if (c->debug & 1) {
+    RT_HIP(launch_nonfinite(c, I, T, stream));
+    unsigned long long h[2];
+    RT_HIP(hipMemcpyAsync(h, c->d_count, sizeof h, hipMemcpyDeviceToHost, stream));
+    RT_HIP(hipStreamSynchronize(stream));
+    RT_HIP(hipMemsetAsync(c->d_count + 1, 0, sizeof(unsigned long long), stream));
+    if (h[1]) return fail(RT_E_NONFINITE, "rt_step: " + std::to_string(h[1]) + " non-finite values");
+    if (h[0]) {
+      set_error("rt_step: " + std::to_string(h[0]) + " cells without a valid temperature root");
+      return RT_W_NEWTON;
+    }
+  }
+  return RT_OK;
+}
+
+rt_status rt_moments(rt_ctx* c, const void* I, double* R, double* J, int frame, hipStream_t stream) {
+  if (!c) return fail(RT_E_ARG, "rt_moments: ctx is NULL");
+  if (!I || !R) return fail(RT_E_ARG, "rt_moments: I and R are required");
+  if (!aligned(I) || !aligned(R) || (J && !aligned(J)))
+    return fail(RT_E_ARG, "rt_moments: arrays must be 256-byte aligned");
+  if (frame != RT_TETRAD && frame != RT_COORD) return fail(RT_E_ARG, "rt_moments: bad frame");
+  rt_status st = use_device(c);
+  if (st) return st;
+  // flat metric: the identity tetrad makes both frames coincide
+  RT_HIP(timed(c, RT_K_MOMENTS, stream, [&] { return launch_moments(c, I, R, J, stream); }));
+  return RT_OK;
+}
+
+rt_status rt_step_adjoint(rt_ctx* c, const void* I_n, const double* T_n, double dt,
+                          const void* gI_np1, void* gI_n, double* g_kappa_a, double* g_j,
+                          hipStream_t stream) {
+  (void)T_n;
+  if (!c) return fail(RT_E_ARG, "rt_step_adjoint: ctx is NULL");
+  if (!c->metric_set || !c->opac_set) return fail(RT_E_STATE, "rt_step_adjoint: set metric and opacities first");
+  if (c->opac.model != RT_OPAC_FIXED_EMISSIVITY)
+    return fail(RT_E_ARG, "rt_step_adjoint: only the FIXED_EMISSIVITY model is differentiated");
+  if (c->moving) return fail(RT_E_ARG, "rt_step_adjoint: fluid must be at rest");
+  if (!I_n || !gI_np1 || !gI_n) return fail(RT_E_ARG, "rt_step_adjoint: NULL intensity argument");
+  if (!(dt > 0.0) || dt > c->dt_max * (1.0 + 1e-12)) return fail(RT_E_ARG, "rt_step_adjoint: bad dt");
+  rt_status st = use_device(c);
+  if (st) return st;
+  const size_t bytes = (size_t)c->ns * c->nc * c->elem;
+  if ((st = alloc(&c->d_gA, bytes)) || (st = alloc(&c->d_gB, bytes)) || (st = alloc(&c->d_gC, bytes)) ||
+      (st = alloc(&c->d_gcell, 4 * (size_t)c->nc * 8)))
+    return st;
+  RT_HIP(timed(c, RT_K_ADJOINT, stream, [&] {
+    return launch_adjoint_step(c, I_n, dt, gI_np1, gI_n, g_kappa_a, g_j, stream);
+  }));
+  return RT_OK;
+}
+
+rt_status rt_set_debug(rt_ctx* c, int flags) {
+  if (!c) return fail(RT_E_ARG, "rt_set_debug: ctx is NULL");
+  c->debug = flags;
+  return RT_OK;
+}
+
+rt_status rt_kernel_times(rt_ctx* c, int* counts, double* ms) {
+  if (!c) return fail(RT_E_ARG, "rt_kernel_times: ctx is NULL");
+  rt_status st = use_device(c);
+  if (st) return st;
+  int cnt[RT_NKERNELS] = {0};
+  double tot[RT_NKERNELS] = {0.0};
+  for (auto& t : c->timed) {
+    RT_HIP(hipEventSynchronize(t.b));
+    float m = 0.f;
+    RT_HIP(hipEventElapsedTime(&m, t.a, t.b));
+    cnt[t.kind] += 1;
+    tot[t.kind] += m;
+    c->event_pool.push_back(t.a);
+    c->event_pool.push_back(t.b);
+  }
+  c->timed.clear();
+  for (int k = 0; k < RT_NKERNELS; ++k) {
+    if (counts) counts[k] = cnt[k];
+    if (ms) ms[k] = tot[k];
+  }
+  return RT_OK;
+}
+
+rt_status rt_newton_failures(rt_ctx* c, long long* count) {
+  if (!c || !count) return fail(RT_E_ARG, "rt_newton_failures: NULL argument");
+  rt_status st = use_device(c);
+  if (st) return st;
+  unsigned long long h = 0;
+  RT_HIP(hipMemcpy(&h, c->d_count, sizeof h, hipMemcpyDeviceToHost));
+  RT_HIP(hipMemset(c->d_count, 0, sizeof h));
+  *count = (long long)h;
+  return RT_OK;
+}
+
+void rt_destroy(rt_ctx* c) {
+  if (!c) return;
+  (void)use_device(c);
+  (void)hipDeviceSynchronize();
+  release(c->d_dir);
+  release(c->d_dir_f);
+  release(c->d_w);
+  release(c->d_W16);
+  release(c->d_rho);
+  release(c->d_uhat);
+  release(c->d_v);
+  release(c->d_ka);
+  release(c->d_ks);
+  release(c->d_j);
+  release(c->d_abar_a);
+  release(c->d_abar_s);
+  release(c->d_ahat);
+  release(c->d_Tstar);
+  for (auto& f : c->d_face) release(f);
+  release(c->d_Itil);
+  release(c->d_Istar);
+  release(c->d_gA);
+  release(c->d_gB);
+  release(c->d_gC);
+  release(c->d_gcell);
+  release(c->d_count);
+  for (auto& t : c->timed) {
+    (void)hipEventDestroy(t.a);
+    (void)hipEventDestroy(t.b);
+  }
+  for (auto e : c->event_pool) (void)hipEventDestroy(e);
+  delete c;
+}
+
+}  // extern "C"

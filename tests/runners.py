@@ -1,0 +1,114 @@
+"""Shared drivers for the parity tests: run one workload through the HIP
+library (via the Python binding) and through the oracle, from the same
+seeded inputs."""
+import math
+
+import numpy as np
+import torch
+
+import workloads as W
+
+F64 = torch.float64
+
+
+def gpu_context(wl, precision="fp64", limiter="mc", cfl=0.4):
+    import paper_2508_15532_amd as P
+    ctx = P.RTContext(wl["n"], wl["xlo"], wl["xhi"], wl["generation"], weights=wl["weights"],
+                      precision=precision, bc=wl["bc"], bc_hi=wl.get("bc_hi"), limiter=limiter)
+    ctx.set_metric("flat", cfl=cfl)
+    dev = torch.device("cuda", 0)
+
+    def t(x):
+        return None if x is None else torch.as_tensor(np.ascontiguousarray(x), dtype=F64).to(dev)
+
+    ctx.set_opacities(wl["model"], t(wl["rho"]), u=t(wl.get("u")), kappa_a=t(wl.get("kappa_a")),
+                      kappa_s=t(wl.get("kappa_s")), j=t(wl.get("j")), gamma=wl["gamma"],
+                      C_a=wl.get("C_a", 1.0), C_s=wl.get("C_s", 1.0),
+                      newton_max_iter=wl.get("newton_max_iter", 50))
+    return ctx
+
+
+def gpu_initial(ctx, wl, I0=None):
+    dev = torch.device("cuda", 0)
+    if I0 is None:
+        iso = torch.as_tensor(np.ascontiguousarray(wl["I0_iso"]), dtype=F64, device=dev)
+        I = iso.reshape(1, -1).expand(ctx.ns, -1).to(ctx.intensity_dtype).contiguous()
+    else:
+        I = torch.as_tensor(np.ascontiguousarray(I0), dtype=F64).reshape(ctx.ns, -1).to(dev)
+        I = I.to(ctx.intensity_dtype).contiguous()
+    T = torch.as_tensor(np.ascontiguousarray(wl["T"]), dtype=F64, device=dev).reshape(-1).contiguous()
+    return I, T
+
+
+def gpu_run(wl, steps, precision="fp64", I0=None, limiter="mc", want_G=False):
+    ctx = gpu_context(wl, precision, limiter)
+    I, T = gpu_initial(ctx, wl, I0)
+    G = torch.zeros((4, ctx.nc), dtype=F64, device=I.device) if want_G else None
+    for _ in range(steps):
+        ctx.step(I, T, wl["dt"], 1, G=G)
+    R = ctx.moments(I)
+    torch.cuda.synchronize()
+    shape = tuple(wl["n"])
+    out = dict(I=I.double().cpu().reshape((ctx.ns,) + shape), T=T.cpu().reshape(shape),
+               R=R.cpu().reshape((10,) + shape))
+    if want_G:
+        out["G"] = G.cpu().reshape((4,) + shape)
+    ctx.close()
+    return out
+
+
+def oracle_run(wl, steps, I0=None, limiter=0, want_G=False):
+    from oracle import step as st
+    from oracle.setup import build_flat
+    pb, I, T = build_flat(wl, limiter=limiter)
+    if I0 is not None:
+        I = torch.as_tensor(I0, dtype=F64).reshape(I.shape).clone()
+    G = None
+    for _ in range(steps):
+        if want_G:
+            I, T, G = st.step(pb, I, T, wl["dt"], want_G=True)
+        else:
+            I, T = st.step(pb, I, T, wl["dt"])
+    g = pb.geo.grid
+    out = dict(I=I, T=T, R=st.moments(I, g.n, g.w))
+    if want_G:
+        out["G"] = G
+    out["failed"] = sum(pb.failed)
+    return out
+
+
+def rel_l2(a, b):
+    return float(torch.linalg.vector_norm(a - b) / max(torch.linalg.vector_norm(b).item(), 1e-300))
+
+
+def rel_max(a, b):
+    return float((a - b).abs().max() / max(b.abs().max().item(), 1e-300))
+
+
+def moments_error(Ra, Rb):
+    """max over the 10 components of ||dR^(ab)||_2 / ||R^00_ref||_2."""
+    ref = torch.linalg.vector_norm(Rb[0]).item()
+    return max(torch.linalg.vector_norm(Ra[k] - Rb[k]).item() for k in range(10)) / ref
+
+
+def J_of(R):
+    return R[0] / (4 * math.pi)
+
+
+def moving_fluid(shape, seed, vmax=0.3):
+    """Random subluminal coordinate 4-velocity u^mu [4, *shape] (flat space)."""
+    rng = np.random.default_rng(seed)
+    v = rng.uniform(-1, 1, (3,) + tuple(shape))
+    v *= vmax / np.maximum(np.sqrt((v ** 2).sum(0)), 1e-12) * rng.uniform(0, 1, tuple(shape))
+    g = 1.0 / np.sqrt(1 - (v ** 2).sum(0))
+    return np.concatenate([g[None], g[None] * v])
+
+
+def patch(field, center, radius):
+    """Periodic cube of side 2*radius+1 around `center` from a [..., n1, n2, n3] array."""
+    idx = [np.arange(c - radius, c + radius + 1) % n for c, n in zip(center, field.shape[-3:])]
+    return field[..., idx[0][:, None, None], idx[1][None, :, None], idx[2][None, None, :]]
+
+
+__all__ = ["W", "gpu_context", "gpu_initial", "gpu_run", "oracle_run", "rel_l2", "rel_max",
+           "moments_error", "J_of", "moving_fluid", "patch"]
