@@ -27,20 +27,17 @@ KERNEL_SRC = os.path.join(ROOT, "paper_2508_15532_amd", "csrc", "kernels.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 
 
-def algorithmic_bytes(kind, elem, ns, nc, moving=False):
+def algorithmic_bytes(kind, elem, ns, nc):
     """Bytes a launch of each kernel must move at minimum (its inputs read once
-    and outputs written once), per launch over the whole grid."""
+    and its outputs written once), per launch over the whole grid."""
     cd = ns * nc
-    cell_face = 3 * 5 * elem          # one set of face coefficients per cell and axis
-    if kind == "transport1":          # read I^n, write I~
-        return 2 * elem * cd + cell_face * nc
-    if kind == "transport2":          # read I*, read I^n, write I~
-        return 3 * elem * cd + cell_face * nc
-    if kind == "source1":             # read I~, write I*; T, rho, abar_a, abar_s, write T*
-        return 2 * elem * cd + 5 * 8 * nc
-    if kind == "source2":             # read I~, write I^n+1; T, T*, rho, abar_a, abar_s, write T
-        return 2 * elem * cd + 6 * 8 * nc
-    if kind == "moments":             # read I, write 10 components
+    if kind == "stage1":       # read I^n, write I~; per cell: map, T, rho in; T*, map out
+        return 2 * elem * cd + 56 * nc
+    if kind == "stage2":       # read I*, I^n, write I~; per cell: 2 maps, T, T*, rho in; T, map, R out
+        return 3 * elem * cd + 160 * nc
+    if kind == "materialize":  # read I~, write I; per cell: map
+        return 2 * elem * cd + 16 * nc
+    if kind == "moments":      # read I, write 10 components
         return elem * cd + 80 * nc
     raise KeyError(kind)
 
@@ -62,28 +59,31 @@ def make_inputs(wl, ctx, torch):
     return rho, I, T, R
 
 
-def run_form(wl, precision, steps, warmup, torch, P):
+def run_form(wl, precision, steps, warmup, torch, P, per_call=False):
+    """Time `steps` steps of rt_step (moments of every step written to R);
+    either one call advancing all steps, or one call per step."""
     ctx = P.RTContext(wl["n"], wl["xlo"], wl["xhi"], wl["generation"], weights=wl["weights"],
                       precision=precision, bc=wl["bc"])
     ctx.set_metric("flat", cfl=0.4)
     rho, I, T, R = make_inputs(wl, ctx, torch)
     dt = wl["dt"]
     for _ in range(warmup):
-        ctx.step(I, T, dt, 1)
-        ctx.moments(I, R)
+        ctx.step(I, T, dt, 1, R=R)
     torch.cuda.synchronize()
     ctx.set_debug(2)                      # HIP events around every launch
     ctx.kernel_times()                    # reset the tally
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(steps):
-        ctx.step(I, T, dt, 1)
-        ctx.moments(I, R)
+    if per_call:
+        for _ in range(steps):
+            ctx.step(I, T, dt, 1, R=R)
+    else:
+        ctx.step(I, T, dt, steps, R=R)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ktimes = ctx.kernel_times()
     ctx.set_debug(0)
-    ok = bool(torch.isfinite(R).all().item())
+    ok = bool(torch.isfinite(R).all().item()) and bool(torch.isfinite(T).all().item())
     ns, nc = ctx.ns, ctx.nc
     ctx.close()
     del I, T, R, rho
@@ -135,6 +135,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--forms", default="fp32,fp64")
+    ap.add_argument("--no-per-call", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU "
@@ -154,13 +155,17 @@ def main():
         print(f"bench: {prec} 128^3 x 162, {args.warmup} warmup + {args.steps} timed steps",
               file=sys.stderr, flush=True)
         res[prec] = run_form(wl, prec, args.steps, args.warmup, torch, P)
+    per_call = None
+    if not args.no_per_call and "fp32" in forms:
+        print("bench: fp32, one rt_step call per step", file=sys.stderr, flush=True)
+        per_call = run_form(wl, "fp32", args.steps, args.warmup, torch, P, per_call=True)
     head = "fp32" if "fp32" in res else forms[0]
     r = res[head]
     cd_per_step = r["ns"] * r["nc"]
     value = cd_per_step * args.steps / r["wall"]
     ms_per_step = 1e3 * r["wall"] / args.steps
     # roofline of the dominant kernel, from HIP events over the timed region
-    kt = {k: v for k, v in r["ktimes"].items() if v[0] > 0 and k not in ("opacity", "faces")}
+    kt = {k: v for k, v in r["ktimes"].items() if v[0] > 0}
     dom = max(kt, key=lambda k: kt[k][1])
     launches, tot_ms = kt[dom]
     avg_s = tot_ms / launches / 1e3
@@ -184,7 +189,9 @@ def main():
         "config": {"workload": "flat 128^3 x 162 directions (geodesic g2), lognormal rho, "
                                "T~U[0.5,2], alpha^a=rho^2 T^-3.5, alpha^s=rho, Method 2, periodic",
                    "form": "fp32 transport + fp64 interaction/moments" if head == "fp32" else "fp64",
-                   "cells": r["nc"], "directions": r["ns"], "step": "rt_step + rt_moments",
+                   "cells": r["nc"], "directions": r["ns"],
+                   "step": "predictor-corrector step incl. R^(ab) of the new intensity; "
+                           "K steps advanced by one rt_step call",
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": dom,
@@ -197,6 +204,9 @@ def main():
         out[f"ms_per_step_{prec}"] = 1e3 * rr["wall"] / args.steps
         if not rr["finite"]:
             out["error"] = f"non-finite moments in the {prec} run"
+    if per_call is not None:
+        out["value_fp32_one_call_per_step"] = per_call["ns"] * per_call["nc"] * args.steps / per_call["wall"]
+        out["ms_per_step_fp32_one_call_per_step"] = 1e3 * per_call["wall"] / args.steps
     if "fp32" in res and "fp64" in res:
         out["speedup_fp32_over_fp64"] = out["value_fp32"] / out["value_fp64"]
     if not args.no_cpu_baseline:

@@ -147,9 +147,12 @@ rt_status rt_set_opacities(rt_ctx* ctx, const rt_opacity_desc* desc, hipStream_t
    I     in/out [Ns][Nc] (element type per precision), T in/out [Nc].
    G_out optional [4][Nc]: tetrad-frame 4-force on the fluid of the last
          step's second interaction, -(R^(0a)(after) - R^(0a)(before))/dt.
+   R_out optional [10][Nc]: moments (as rt_moments, tetrad frame) of the new
+         intensity, computed inside every step from the FP64 interaction
+         state; on return it holds those of the last step.
    0 < dt <= dt_max of rt_set_metric, else RT_E_ARG. */
 rt_status rt_step(rt_ctx* ctx, void* I, double* T, double dt, int nsteps, double* G_out,
-                  hipStream_t stream);
+                  double* R_out, hipStream_t stream);
 
 /* Moments (Eq. R): R[k][c] = sum_s w_s n^a n^b I[s][c] for the 10 pairs
    (a,b) = 00,01,02,03,11,12,13,22,23,33 (n^0 = 1), accumulated in FP64.
@@ -177,8 +180,8 @@ rt_status rt_set_debug(rt_ctx* ctx, int flags);
    and returns, for each kernel kind k < RT_NKERNELS, the number of launches
    (counts[k]) and their summed duration in milliseconds (ms[k]) since the
    previous call, then starts a new tally.  Either output may be NULL. */
-enum { RT_K_OPACITY = 0, RT_K_FACES, RT_K_TRANSPORT1, RT_K_TRANSPORT2, RT_K_SOURCE1,
-       RT_K_SOURCE2, RT_K_MOMENTS, RT_K_ADJOINT, RT_NKERNELS };
+enum { RT_K_STAGE1 = 0, RT_K_STAGE2, RT_K_MATERIALIZE, RT_K_MOMENTS, RT_K_ADJOINT,
+       RT_NKERNELS };
 rt_status rt_kernel_times(rt_ctx* ctx, int* counts, double* ms);
 
 /* Number of interaction failures counted since the last call (debug mode). */

@@ -131,12 +131,15 @@ class RTContext:
         self._keep = [rho, u, kappa_a, kappa_s, j]
 
     # -- hot path -------------------------------------------------------------
-    def step(self, I, T, dt, nsteps=1, G=None):
-        """Advance (I, T) in place by nsteps predictor-corrector steps."""
+    def step(self, I, T, dt, nsteps=1, G=None, R=None):
+        """Advance (I, T) in place by nsteps predictor-corrector steps; optional
+        G [4, Nc] (4-force of the last step) and R [10, Nc] (moments of the new
+        intensity) are filled in."""
         import torch
         st = self._lib.rt_step(self._ctx, _ptr(I, "I", self.intensity_dtype, self.ns * self.nc),
                                _ptr(T, "T", torch.float64, self.nc), float(dt), int(nsteps),
-                               _ptr(G, "G", torch.float64, 4 * self.nc, optional=True), _stream())
+                               _ptr(G, "G", torch.float64, 4 * self.nc, optional=True),
+                               _ptr(R, "R", torch.float64, 10 * self.nc, optional=True), _stream())
         return N.check(st, allow_warning=True)
 
     def moments(self, I, R=None, J=None, frame="tetrad"):

@@ -21,7 +21,7 @@ RT_LIM_MC, RT_LIM_MINMOD = 0, 1
 RT_FLAT, RT_KERR_SCHILD = 0, 1
 RT_OPAC_KIRCHHOFF_CONST, RT_OPAC_BREMS, RT_OPAC_FIXED_EMISSIVITY = 0, 1, 2
 RT_TETRAD, RT_COORD = 0, 1
-KERNELS = ["opacity", "faces", "transport1", "transport2", "source1", "source2", "moments", "adjoint"]
+KERNELS = ["stage1", "stage2", "materialize", "moments", "adjoint"]
 
 EXPORTED = ["rt_init_grid", "rt_geodesic_grid", "rt_grid_info", "rt_set_metric", "rt_set_opacities", "rt_step",
             "rt_moments", "rt_step_adjoint", "rt_set_debug", "rt_kernel_times", "rt_newton_failures",
@@ -63,7 +63,7 @@ def load():
         "rt_grid_info": ([P, C.POINTER(I), P, P, P], I),
         "rt_set_metric": ([P, I, D, D, D, C.POINTER(D)], I),
         "rt_set_opacities": ([P, C.POINTER(OpacityDesc), P], I),
-        "rt_step": ([P, P, P, D, I, P, P], I),
+        "rt_step": ([P, P, P, D, I, P, P, P], I),
         "rt_moments": ([P, P, P, P, I, P], I),
         "rt_step_adjoint": ([P, P, P, D, P, P, P, P, P], I),
         "rt_set_debug": ([P, I], I),

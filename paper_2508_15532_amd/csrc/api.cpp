@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "ctx.hpp"
+#include "stage.hpp"
 
 namespace rt {
 namespace {
@@ -164,6 +165,10 @@ rt_status rt_init_grid(const rt_grid_desc* d, rt_ctx** out) {
     static const int pb[10] = {0, 1, 2, 3, 1, 2, 3, 2, 3, 3};
     for (int k = 0; k < 10; ++k) W16[(size_t)s * 16 + k] = w[s] * n4[pa[k]] * n4[pb[k]];
   }
+  for (int s = 0; s < ns; ++s) {
+    c->W0 += w[s];
+    for (int k = 0; k < 10; ++k) c->Wsum[k] += W16[(size_t)s * 16 + k];
+  }
   rt_status st = RT_OK;
   if ((st = alloc(&c->d_dir, dir.size() * 8)) || (st = alloc(&c->d_dir_f, dirf.size() * 4)) ||
       (st = alloc(&c->d_w, w.size() * 8)) || (st = alloc(&c->d_W16, W16.size() * 8)) ||
@@ -231,18 +236,10 @@ rt_status rt_set_metric(rt_ctx* c, int kind, double M, double a, double cfl, dou
   double dtm = INFINITY;
   for (int k = 0; k < 3; ++k) dtm = std::min(dtm, c->dx[k] / vmax[k]);
   c->dt_max = cfl * dtm;
-  // per-stage scratch
+  // per-stage scratch: one intensity copy (the half-step state) and two lazy maps
   const size_t nc = (size_t)c->nc, ns = (size_t)c->ns;
-  const size_t fel = c->fp32 ? 4 : 8;
-  c->nface[0] = (long long)(c->n[0] + 1) * c->n[1] * c->n[2];
-  c->nface[1] = (long long)c->n[0] * (c->n[1] + 1) * c->n[2];
-  c->nface[2] = (long long)c->n[0] * c->n[1] * (c->n[2] + 1);
-  if ((st = alloc(&c->d_abar_a, nc * 8)) || (st = alloc(&c->d_abar_s, nc * 8)) ||
-      (st = alloc(&c->d_ahat, nc * 8)) || (st = alloc(&c->d_Tstar, nc * 8)) ||
-      (st = alloc(&c->d_face[0], 5 * c->nface[0] * fel)) ||
-      (st = alloc(&c->d_face[1], 5 * c->nface[1] * fel)) ||
-      (st = alloc(&c->d_face[2], 5 * c->nface[2] * fel)) ||
-      (st = alloc(&c->d_Itil, ns * nc * c->elem)) || (st = alloc(&c->d_Istar, ns * nc * c->elem)))
+  if ((st = alloc(&c->d_Tstar, nc * 8)) || (st = alloc(&c->d_mapA, 3 * nc * 8)) ||
+      (st = alloc(&c->d_mapB, 3 * nc * 8)) || (st = alloc(&c->d_Itil, ns * nc * c->elem)))
     return st;
   c->metric_set = true;
   if (dt_max_out) *dt_max_out = c->dt_max;
@@ -290,34 +287,102 @@ rt_status rt_set_opacities(rt_ctx* c, const rt_opacity_desc* o, hipStream_t stre
 }
 
 rt_status rt_step(rt_ctx* c, void* I, double* T, double dt, int nsteps, double* G_out,
-                  hipStream_t stream) {
+                  double* R_out, hipStream_t stream) {
   if (!c) return fail(RT_E_ARG, "rt_step: ctx is NULL");
   if (!c->metric_set || !c->opac_set) return fail(RT_E_STATE, "rt_step: set metric and opacities first");
   if (!I || !T) return fail(RT_E_ARG, "rt_step: I and T are required");
-  if (!aligned(I) || !aligned(T) || (G_out && !aligned(G_out)))
+  if (!aligned(I) || !aligned(T) || (G_out && !aligned(G_out)) || (R_out && !aligned(R_out)))
     return fail(RT_E_ARG, "rt_step: arrays must be 256-byte aligned");
   if (nsteps < 0) return fail(RT_E_ARG, "rt_step: nsteps must be >= 0");
   if (!(dt > 0.0) || dt > c->dt_max * (1.0 + 1e-12))
     return fail(RT_E_ARG, "rt_step: need 0 < dt <= dt_max (" + std::to_string(c->dt_max) + ")");
   rt_status st = use_device(c);
   if (st) return st;
+  StageArgs a{};
+  a.n1 = c->n[0];
+  a.n2 = c->n[1];
+  a.n3 = c->n[2];
+  a.nc = c->nc;
+  a.ns = c->ns;
+  for (int ax = 0; ax < 3; ++ax) {
+    a.bc_lo[ax] = c->desc.bc_lo[ax];
+    a.bc_hi[ax] = c->desc.bc_hi[ax];
+    a.inv_dx[ax] = 1.0 / c->dx[ax];
+  }
+  a.dt = dt;
+  a.abar = c->desc.abar;
+  a.limiter = c->desc.limiter;
+  a.model = c->opac.model;
+  a.gamma = c->opac.gamma;
+  a.C_a = c->opac.C_a;
+  a.C_s = c->opac.C_s;
+  a.rho_floor = c->desc.rho_floor;
+  a.max_iter = c->opac.newton_max_iter;
+  a.rtol = c->opac.newton_rtol;
+  a.W0 = c->W0;
+  for (int k = 0; k < 10; ++k) a.Wsum[k] = c->Wsum[k];
+  StagePtrs p{};
+  p.rho = c->d_rho;
+  p.ka = c->d_ka;
+  p.ks = c->d_ks;
+  p.jv = c->d_j;
+  p.uhat = c->d_uhat;
+  p.vel = c->d_v;
+  p.dirF_v = c->fp32 ? (const void*)c->d_dir_f : (const void*)c->d_dir;
+  p.dirD = c->d_dir;
+  p.w = c->d_w;
+  p.W16 = c->d_W16;
+  p.fail = c->d_count;
+  const double* mapA = nullptr;  // the caller's I is materialised on entry
   for (int k = 0; k < nsteps; ++k) {
-    bool last = k == nsteps - 1;
+    const bool last = k == nsteps - 1;
     // stage 1: fluxes of I^n, half step, interaction from T^n with opacities at T^n
-    RT_HIP(timed(c, RT_K_OPACITY, stream, [&] { return launch_opacity(c, T, stream); }));
-    RT_HIP(timed(c, RT_K_FACES, stream, [&] { return launch_faces(c, dt, stream); }));
-    RT_HIP(timed(c, RT_K_TRANSPORT1, stream,
-                 [&] { return launch_transport(c, I, I, c->d_Itil, 0.5 * dt, stream); }));
-    RT_HIP(timed(c, RT_K_SOURCE1, stream, [&] {
-      return launch_source(c, c->d_Itil, c->d_Istar, T, T, c->d_Tstar, 0.5 * dt, nullptr, stream);
-    }));
+    a.h = 0.5 * dt;
+    p.Iflux_v = I;
+    p.mapF = mapA;
+    p.Ibase_v = nullptr;
+    p.mapB = nullptr;
+    p.Iout_v = c->d_Itil;
+    p.mapO = c->d_mapB;
+    p.Tstart = T;
+    p.Tcoef = T;
+    p.Tout = c->d_Tstar;
+    p.Rout = nullptr;
+    p.Gout = nullptr;
+    RT_HIP(timed(c, RT_K_STAGE1, stream, [&] { return launch_stage(c, a, p, false, stream); }));
+    const double* mapB = c->d_mapB;
+    if (c->moving) {
+      RT_HIP(timed(c, RT_K_MATERIALIZE, stream, [&] {
+        return launch_materialize(c, c->d_Itil, c->d_mapB, a.h, nullptr, nullptr, stream);
+      }));
+      mapB = nullptr;
+    }
     // stage 2: fluxes of I*, full step from I^n, energy balance from T^n, opacities at T*
-    RT_HIP(timed(c, RT_K_OPACITY, stream, [&] { return launch_opacity(c, c->d_Tstar, stream); }));
-    RT_HIP(timed(c, RT_K_FACES, stream, [&] { return launch_faces(c, dt, stream); }));
-    RT_HIP(timed(c, RT_K_TRANSPORT2, stream,
-                 [&] { return launch_transport(c, c->d_Istar, I, c->d_Itil, dt, stream); }));
-    RT_HIP(timed(c, RT_K_SOURCE2, stream, [&] {
-      return launch_source(c, c->d_Itil, I, T, c->d_Tstar, T, dt, last ? G_out : nullptr, stream);
+    a.h = dt;
+    p.Iflux_v = c->d_Itil;
+    p.mapF = mapB;
+    p.Ibase_v = I;
+    p.mapB = mapA;
+    p.Iout_v = I;
+    p.mapO = c->d_mapA;
+    p.Tstart = T;
+    p.Tcoef = c->d_Tstar;
+    p.Tout = T;
+    p.Rout = c->moving ? nullptr : R_out;
+    p.Gout = (c->moving || !last) ? nullptr : G_out;
+    RT_HIP(timed(c, RT_K_STAGE2, stream, [&] { return launch_stage(c, a, p, true, stream); }));
+    if (c->moving) {
+      RT_HIP(timed(c, RT_K_MATERIALIZE, stream, [&] {
+        return launch_materialize(c, I, c->d_mapA, dt, R_out, last ? G_out : nullptr, stream);
+      }));
+      mapA = nullptr;
+    } else {
+      mapA = c->d_mapA;
+    }
+  }
+  if (mapA) {
+    RT_HIP(timed(c, RT_K_MATERIALIZE, stream, [&] {
+      return launch_materialize(c, I, mapA, dt, nullptr, nullptr, stream);
     }));
   }
   if (c->debug & 1) {
@@ -351,22 +416,24 @@ rt_status rt_moments(rt_ctx* c, const void* I, double* R, double* J, int frame, 
 rt_status rt_step_adjoint(rt_ctx* c, const void* I_n, const double* T_n, double dt,
                           const void* gI_np1, void* gI_n, double* g_kappa_a, double* g_j,
                           hipStream_t stream) {
-  (void)T_n;
   if (!c) return fail(RT_E_ARG, "rt_step_adjoint: ctx is NULL");
   if (!c->metric_set || !c->opac_set) return fail(RT_E_STATE, "rt_step_adjoint: set metric and opacities first");
   if (c->opac.model != RT_OPAC_FIXED_EMISSIVITY)
     return fail(RT_E_ARG, "rt_step_adjoint: only the FIXED_EMISSIVITY model is differentiated");
   if (c->moving) return fail(RT_E_ARG, "rt_step_adjoint: fluid must be at rest");
-  if (!I_n || !gI_np1 || !gI_n) return fail(RT_E_ARG, "rt_step_adjoint: NULL intensity argument");
+  if (!I_n || !T_n || !gI_np1 || !gI_n) return fail(RT_E_ARG, "rt_step_adjoint: NULL argument");
+  if (!aligned(I_n) || !aligned(T_n) || !aligned(gI_np1) || !aligned(gI_n) ||
+      (g_kappa_a && !aligned(g_kappa_a)) || (g_j && !aligned(g_j)))
+    return fail(RT_E_ARG, "rt_step_adjoint: arrays must be 256-byte aligned");
   if (!(dt > 0.0) || dt > c->dt_max * (1.0 + 1e-12)) return fail(RT_E_ARG, "rt_step_adjoint: bad dt");
   rt_status st = use_device(c);
   if (st) return st;
   const size_t bytes = (size_t)c->ns * c->nc * c->elem;
   if ((st = alloc(&c->d_gA, bytes)) || (st = alloc(&c->d_gB, bytes)) || (st = alloc(&c->d_gC, bytes)) ||
-      (st = alloc(&c->d_gcell, 4 * (size_t)c->nc * 8)))
+      (st = alloc(&c->d_gD, bytes)) || (st = alloc(&c->d_gcell, 6 * (size_t)c->nc * 8)))
     return st;
   RT_HIP(timed(c, RT_K_ADJOINT, stream, [&] {
-    return launch_adjoint_step(c, I_n, dt, gI_np1, gI_n, g_kappa_a, g_j, stream);
+    return launch_adjoint_step(c, I_n, T_n, dt, gI_np1, gI_n, g_kappa_a, g_j, stream);
   }));
   return RT_OK;
 }
@@ -425,16 +492,14 @@ void rt_destroy(rt_ctx* c) {
   release(c->d_ka);
   release(c->d_ks);
   release(c->d_j);
-  release(c->d_abar_a);
-  release(c->d_abar_s);
-  release(c->d_ahat);
   release(c->d_Tstar);
-  for (auto& f : c->d_face) release(f);
+  release(c->d_mapA);
+  release(c->d_mapB);
   release(c->d_Itil);
-  release(c->d_Istar);
   release(c->d_gA);
   release(c->d_gB);
   release(c->d_gC);
+  release(c->d_gD);
   release(c->d_gcell);
   release(c->d_count);
   for (auto& t : c->timed) {

@@ -43,18 +43,17 @@ struct rt_ctx {
   double* d_j = nullptr;
 
   // per-stage scratch
-  double* d_abar_a = nullptr;  // [nc] fluid-frame absorption at T_coef
-  double* d_abar_s = nullptr;  // [nc] scattering
-  double* d_ahat = nullptr;    // [nc] u-hat^0 (abar_a + abar_s)
   double* d_Tstar = nullptr;   // [nc]
-  void* d_face[3] = {nullptr, nullptr, nullptr};  // per axis [5][nfaces]
-  long long nface[3] = {0, 0, 0};
-  void* d_Itil = nullptr;      // [ns][nc] transported, pre-interaction intensity
-  void* d_Istar = nullptr;     // [ns][nc] half-step intensity
+  void* d_Itil = nullptr;      // [ns][nc] stage-1 output (I~ of the half step)
+  double* d_mapA = nullptr;    // [3][nc] lazy interaction map of the state buffer
+  double* d_mapB = nullptr;    // [3][nc] lazy interaction map of d_Itil
+  double W0 = 0.0;             // sum of the weights
+  double Wsum[10] = {0};       // sum_s w_s n^a n^b
   void* d_gA = nullptr;        // adjoint scratch [ns][nc] x 3
   void* d_gB = nullptr;
   void* d_gC = nullptr;
-  double* d_gcell = nullptr;   // adjoint per-cell scratch [4][nc]
+  void* d_gD = nullptr;
+  double* d_gcell = nullptr;   // adjoint per-face tau gradients [3][2][nc]
   unsigned long long* d_count = nullptr;  // [0] interaction failures, [1] non-finite
   int debug = 0;
   // kernel timing (debug bit 1): events recorded around launches
@@ -72,16 +71,10 @@ void set_error(const std::string& msg);
 
 // all launchers enqueue on `st` and return the launch status
 hipError_t launch_fluid(rt_ctx* c, const double* u, hipStream_t st);
-hipError_t launch_opacity(rt_ctx* c, const double* T_coef, hipStream_t st);
-hipError_t launch_faces(rt_ctx* c, double dt, hipStream_t st);
-hipError_t launch_transport(rt_ctx* c, const void* I_flux, const void* I_base, void* I_out,
-                            double h, hipStream_t st);
-hipError_t launch_source(rt_ctx* c, const void* I_til, void* I_out, const double* T_start,
-                         const double* T_coef, double* T_out, double h, double* G,
-                         hipStream_t st);
 hipError_t launch_moments(rt_ctx* c, const void* I, double* R, double* J, hipStream_t st);
 hipError_t launch_nonfinite(rt_ctx* c, const void* I, const double* T, hipStream_t st);
-hipError_t launch_adjoint_step(rt_ctx* c, const void* I_n, double dt, const void* gI_np1,
-                               void* gI_n, double* g_ka, double* g_j, hipStream_t st);
+hipError_t launch_adjoint_step(rt_ctx* c, const void* I_n, const double* T_n, double dt,
+                               const void* gI_np1, void* gI_n, double* g_ka, double* g_j,
+                               hipStream_t st);
 
 }  // namespace rt

@@ -1,12 +1,10 @@
-// HIP kernels (gfx950) of the gray transfer step: per-cell opacities, per-face
-// flux coefficients, the per-(cell, direction) transport update, the per-cell
-// implicit interaction, and the MFMA moment contraction.
+// HIP kernels (gfx950) outside the fused stage: fluid-velocity setup, the
+// FP64 MFMA moment contraction and the non-finite check.
 //
 // Data layout: intensities direction-major I[s*nc + c], c = (i1*n2 + i2)*n3 + i3,
 // so a wavefront's 64 lanes read 64 consecutive cells of one direction.
 // Template parameter S is the intensity storage type (float in the FP32
-// transport form, double otherwise); the interaction and the moments always
-// compute in double.
+// transport form, double otherwise); the moments always accumulate in double.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -18,364 +16,6 @@ namespace {
 
 constexpr double kPi = 3.14159265358979323846;
 constexpr int kBlock = 256;
-
-struct Dims {
-  int n1, n2, n3;
-  long long nc;
-  int ns;
-};
-
-Dims dims_of(const rt_ctx* c) { return Dims{c->n[0], c->n[1], c->n[2], c->nc, c->ns}; }
-
-__device__ __forceinline__ int wrap_or_clamp(int i, int n, bool periodic) {
-  if (periodic) {
-    i %= n;
-    return i < 0 ? i + n : i;
-  }
-  return i < 0 ? 0 : (i >= n ? n - 1 : i);
-}
-
-// limited PLI slope (Sec. 3.4): MC = minmod(2p, 2q, (p+q)/2), or minmod(p, q)
-template <typename T>
-__device__ __forceinline__ T slope(T p, T q, int limiter) {
-  if (!(p * q > T(0))) return T(0);
-  T ap = fabs(p), aq = fabs(q);
-  T m = limiter == RT_LIM_MC ? fmin(fmin(T(2) * ap, T(2) * aq), T(0.5) * fabs(p + q)) : fmin(ap, aq);
-  return p > T(0) ? m : -m;
-}
-
-// ---------------------------------------------------------------------------
-// per-cell opacities at T_coef (Sec. 3.6.2); zero below the density floor
-// ---------------------------------------------------------------------------
-__global__ void k_opacity(long long nc, int model, double C_a, double C_s, double rho_floor,
-                          const double* __restrict__ rho, const double* __restrict__ T,
-                          const double* __restrict__ ka, const double* __restrict__ ks,
-                          const double* __restrict__ uhat0, double* __restrict__ abar_a,
-                          double* __restrict__ abar_s, double* __restrict__ ahat) {
-  long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= nc) return;
-  double r = rho[c];
-  double aa, as;
-  if (model == RT_OPAC_BREMS) {
-    aa = C_a * r * r * pow(T[c], -3.5);
-    as = C_s * r;
-  } else {
-    aa = ka ? r * ka[c] : 0.0;
-    as = ks ? r * ks[c] : 0.0;
-  }
-  if (!(r >= rho_floor)) aa = as = 0.0;
-  abar_a[c] = aa;
-  abar_s[c] = as;
-  ahat[c] = uhat0[c] * (aa + as);
-}
-
-// ---------------------------------------------------------------------------
-// per-face flux coefficients (Sec. 3.5, direction independent):
-//   tau = abar (ahat_L + ahat_R)/2 dt,  E = exp(-tau),
-//   f2 = sqrt(1 - exp(-tau^2))/tau,  f4 = sqrt(1 - exp(-tau^4))/tau,
-//   Wu = f2/(f2 + f4) (weight of the upwind state), Dc = f2 f4/(f2 + f4),
-//   aL = (1 - E) max(v_L, 0), aR = (1 - E) min(v_R, 0) (advection, PLI of v).
-// Planes of the output: [0] E, [1] Wu, [2] Dc, [3] aL, [4] aR.
-// Faces along axis a: index f = 0..n_a, face f is the lower face of cell f.
-// ---------------------------------------------------------------------------
-template <typename F>
-__global__ void k_faces(Dims d, int axis, bool periodic, double abar, double dt, int limiter,
-                        const double* __restrict__ ahat, const double* __restrict__ v,
-                        F* __restrict__ out, long long nf) {
-  long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= nf) return;
-  int m2 = d.n2 + (axis == 1), m3 = d.n3 + (axis == 2);
-  int f3 = (int)(k % m3);
-  int f2 = (int)((k / m3) % m2);
-  int f1 = (int)(k / ((long long)m3 * m2));
-  int f = axis == 0 ? f1 : (axis == 1 ? f2 : f3);
-  int na = axis == 0 ? d.n1 : (axis == 1 ? d.n2 : d.n3);
-  long long stride = axis == 0 ? (long long)d.n2 * d.n3 : (axis == 1 ? d.n3 : 1);
-  long long base = ((long long)(axis == 0 ? 0 : f1) * d.n2 + (axis == 1 ? 0 : f2)) * d.n3 +
-                   (axis == 2 ? 0 : f3);
-  auto cell = [&](int i) { return base + (long long)wrap_or_clamp(i, na, periodic) * stride; };
-  double tau = abar * 0.5 * (ahat[cell(f - 1)] + ahat[cell(f)]) * dt;
-  double E = exp(-tau);
-  double fa, fb;
-  if (tau < 1e-4) {
-    double t2 = tau * tau;
-    fa = 1.0 - 0.25 * t2;
-    fb = tau * (1.0 - 0.25 * t2 * t2);
-  } else {
-    double t2 = tau * tau;
-    fa = sqrt(-expm1(-t2)) / tau;
-    fb = sqrt(-expm1(-t2 * t2)) / tau;
-  }
-  double Wu = fa / (fa + fb);
-  double Dc = fa * fb / (fa + fb);
-  double aL = 0.0, aR = 0.0;
-  if (v) {
-    const double* va = v + (long long)axis * d.nc;
-    double vm2 = va[cell(f - 2)], vm1 = va[cell(f - 1)], v0 = va[cell(f)], vp1 = va[cell(f + 1)];
-    double vL = vm1 + 0.5 * slope(vm1 - vm2, v0 - vm1, limiter);
-    double vR = v0 - 0.5 * slope(v0 - vm1, vp1 - v0, limiter);
-    aL = (1.0 - E) * fmax(vL, 0.0);
-    aR = (1.0 - E) * fmin(vR, 0.0);
-  }
-  out[k] = (F)E;
-  out[nf + k] = (F)Wu;
-  out[2 * nf + k] = (F)Dc;
-  out[3 * nf + k] = (F)aL;
-  out[4 * nf + k] = (F)aR;
-}
-
-// ---------------------------------------------------------------------------
-// transport (Eq. radiative_transfer_discrete, flat metric: n^0 n_0 = -1 cancels)
-//   I~ = I_base - h sum_a (F_(l+1/2) - F_(l-1/2)) / dx_a,
-//   F = E nu (Wu I_up + (1-Wu) I_dn) - |nu| Dc (I_(l+1) - I_l) + aL I_L + aR I_R
-// with I_L, I_R the PLI states of I_flux at the face and nu = n-hat^a.
-// One thread per cell; blockIdx.y selects a chunk of directions, so the six
-// faces' coefficients are loaded once and reused across the chunk.
-// ---------------------------------------------------------------------------
-struct TransportArgs {
-  Dims d;
-  int bc_lo[3], bc_hi[3];
-  double inv_dx[3];
-  double h;
-  int limiter;
-  int chunk;
-};
-
-template <typename S, typename F>
-__global__ void __launch_bounds__(kBlock)
-k_transport(TransportArgs a, const S* __restrict__ Iflux, const S* __restrict__ Ibase,
-            S* __restrict__ Iout, const F* __restrict__ fx, const F* __restrict__ fy,
-            const F* __restrict__ fz, const F* __restrict__ dir) {
-  const Dims d = a.d;
-  long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= d.nc) return;
-  const int i3 = (int)(c % d.n3);
-  const int i2 = (int)((c / d.n3) % d.n2);
-  const int i1 = (int)(c / ((long long)d.n3 * d.n2));
-  const int ii[3] = {i1, i2, i3};
-  const int nn[3] = {d.n1, d.n2, d.n3};
-  const long long st[3] = {(long long)d.n2 * d.n3, d.n3, 1};
-
-  // neighbour cells at offsets -2..2 and ghost kind (0 interior/copy,
-  // 1 zero when nu > 0, 2 zero when nu < 0)
-  long long nb[3][5];
-  int gk[3][5];
-  for (int ax = 0; ax < 3; ++ax) {
-    bool per = a.bc_lo[ax] == RT_BC_PERIODIC;
-    for (int o = -2; o <= 2; ++o) {
-      int j = ii[ax] + o;
-      int g = 0;
-      if (j < 0 && a.bc_lo[ax] == RT_BC_ZERO_INCOMING) g = 1;
-      if (j >= nn[ax] && a.bc_hi[ax] == RT_BC_ZERO_INCOMING) g = 2;
-      nb[ax][o + 2] = c + (long long)(wrap_or_clamp(j, nn[ax], per) - ii[ax]) * st[ax];
-      gk[ax][o + 2] = g;
-    }
-  }
-  // face coefficients: lower / upper face of this cell along each axis
-  const F* fp[3] = {fx, fy, fz};
-  long long nf[3], flo[3], fhi[3];
-  nf[0] = (long long)(d.n1 + 1) * d.n2 * d.n3;
-  nf[1] = (long long)d.n1 * (d.n2 + 1) * d.n3;
-  nf[2] = (long long)d.n1 * d.n2 * (d.n3 + 1);
-  flo[0] = ((long long)i1 * d.n2 + i2) * d.n3 + i3;
-  fhi[0] = flo[0] + (long long)d.n2 * d.n3;
-  flo[1] = ((long long)i1 * (d.n2 + 1) + i2) * d.n3 + i3;
-  fhi[1] = flo[1] + d.n3;
-  flo[2] = ((long long)i1 * d.n2 + i2) * (d.n3 + 1) + i3;
-  fhi[2] = flo[2] + 1;
-  F cE[3][2], cW[3][2], cD[3][2], cL[3][2], cR[3][2];
-  for (int ax = 0; ax < 3; ++ax) {
-    const F* p = fp[ax];
-    long long idx[2] = {flo[ax], fhi[ax]};
-    for (int u = 0; u < 2; ++u) {
-      cE[ax][u] = p[idx[u]];
-      cW[ax][u] = p[nf[ax] + idx[u]];
-      cD[ax][u] = p[2 * nf[ax] + idx[u]];
-      cL[ax][u] = p[3 * nf[ax] + idx[u]];
-      cR[ax][u] = p[4 * nf[ax] + idx[u]];
-    }
-  }
-  const int s0 = blockIdx.y * a.chunk;
-  const int s1 = min(d.ns, s0 + a.chunk);
-  for (int s = s0; s < s1; ++s) {
-    const long long off = (long long)s * d.nc;
-    const S* Is = Iflux + off;
-    F center = (F)Is[c];
-    F div = F(0);
-    for (int ax = 0; ax < 3; ++ax) {
-      F nu = dir[ax * d.ns + s];
-      F v[5];
-      for (int o = 0; o < 5; ++o) {
-        if (o == 2) {
-          v[o] = center;
-          continue;
-        }
-        int g = gk[ax][o];
-        bool zero = (g == 1 && nu > F(0)) || (g == 2 && nu < F(0));
-        v[o] = zero ? F(0) : (F)Is[nb[ax][o]];
-      }
-      F dm = slope(v[1] - v[0], v[2] - v[1], a.limiter);
-      F d0 = slope(v[2] - v[1], v[3] - v[2], a.limiter);
-      F dp = slope(v[3] - v[2], v[4] - v[3], a.limiter);
-      F flux[2];
-      for (int u = 0; u < 2; ++u) {
-        F IcL = v[1 + u], IcR = v[2 + u];
-        F IL = IcL + F(0.5) * (u == 0 ? dm : d0);
-        F IR = IcR - F(0.5) * (u == 0 ? d0 : dp);
-        F Iup = nu > F(0) ? IL : IR;
-        F Idn = nu > F(0) ? IR : IL;
-        F W = cW[ax][u];
-        flux[u] = cE[ax][u] * nu * (W * Iup + (F(1) - W) * Idn) - fabs(nu) * cD[ax][u] * (IcR - IcL) +
-                  cL[ax][u] * IL + cR[ax][u] * IR;
-      }
-      div += (flux[1] - flux[0]) * (F)a.inv_dx[ax];
-    }
-    Iout[off + c] = (S)((F)Ibase[off + c] - (F)a.h * div);
-  }
-}
-
-// ---------------------------------------------------------------------------
-// implicit interaction per cell (Sec. 3.6.2), all arithmetic in double:
-//   nbar0 = u0 - u.n_s, Ibar = I nbar0^4, dObar = w/nbar0^2,
-//   c_s = n0/(n0 + nbar0 alpha h), d_s = nbar0 h/(4 pi (n0 + nbar0 alpha h)),
-//   Ebar_- = sum Ibar dObar, A1 = sum c Ibar dObar, A2 = sum d dObar,
-//   Y = rho/(gamma-1), q = 1 - A2 alpha^s, K = A1 - Y q T_start - q Ebar_-;
-//   Method 1: A2 alpha^a T^4 + Y q T + K = 0 (Newton from above the root),
-//   Method 2: A2 N sqrt(T) + Y q T + K = 0 (N = C_a rho^2), exact root of the
-//             quadratic in sqrt(T); fixed emissivity: S = 4 pi j, T fixed;
-//   Ebar_+ = Ebar_- - Y (T_+ - T_start) (or (A1 + A2 S)/q), and
-//   I_out = (c Ibar + d (S + alpha^s Ebar_+)) / nbar0^4.
-// One thread per cell, two passes over the directions.
-// ---------------------------------------------------------------------------
-struct SourceArgs {
-  long long nc;
-  int ns;
-  int model;
-  double gamma, C_a, rho_floor, h;
-  int max_iter;
-  double rtol;
-  int moving;
-};
-
-template <typename S>
-__global__ void __launch_bounds__(kBlock)
-k_source(SourceArgs a, const S* __restrict__ It, S* __restrict__ Iout,
-         const double* __restrict__ Tstart, const double* __restrict__ Tcoef,
-         double* __restrict__ Tout, const double* __restrict__ rho,
-         const double* __restrict__ uhat, const double* __restrict__ abar_a,
-         const double* __restrict__ abar_s, const double* __restrict__ jv,
-         const double* __restrict__ dir, const double* __restrict__ w, double* __restrict__ G,
-         unsigned long long* __restrict__ fail) {
-  long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= a.nc) return;
-  const double T0 = Tstart[c];
-  const double r = rho[c];
-  const double n0 = 1.0;  // flat metric, normal-observer tetrad: n^0 = 1
-  if (!(r >= a.rho_floor)) {
-    for (int s = 0; s < a.ns; ++s) Iout[(long long)s * a.nc + c] = It[(long long)s * a.nc + c];
-    Tout[c] = T0;
-    if (G)
-      for (int k = 0; k < 4; ++k) G[k * a.nc + c] = 0.0;
-    return;
-  }
-  double u0 = 1.0, u1 = 0.0, u2 = 0.0, u3 = 0.0;
-  if (a.moving) {
-    u0 = uhat[c];
-    u1 = uhat[a.nc + c];
-    u2 = uhat[2 * a.nc + c];
-    u3 = uhat[3 * a.nc + c];
-  }
-  const double aa = abar_a[c], as = abar_s[c], ab = aa + as, h = a.h;
-  double Em = 0.0, A1 = 0.0, A2 = 0.0;
-  for (int s = 0; s < a.ns; ++s) {
-    double nb = u0 - (u1 * dir[s] + u2 * dir[a.ns + s] + u3 * dir[2 * a.ns + s]);
-    double nb2 = nb * nb;
-    double Ib = (double)It[(long long)s * a.nc + c] * nb2 * nb2;
-    double dOb = w[s] / nb2;
-    double den = n0 + nb * ab * h;
-    double cs = n0 / den;
-    double ds = nb * h / (4.0 * kPi * den);
-    Em += Ib * dOb;
-    A1 += cs * Ib * dOb;
-    A2 += ds * dOb;
-  }
-  const double Y = r / (a.gamma - 1.0);
-  const double q = 1.0 - A2 * as;
-  const double K = A1 - Y * q * T0 - q * Em;
-  double Tp = T0, Sp = 0.0, Ep = 0.0;
-  bool ok = true;
-  if (a.model == RT_OPAC_FIXED_EMISSIVITY) {
-    Sp = 4.0 * kPi * (jv ? jv[c] : 0.0);
-    Ep = (A1 + A2 * Sp) / q;
-  } else {
-    ok = (K < 0.0) && (q > 0.0);
-    if (ok) {
-      const double b = Y * q;
-      if (a.model == RT_OPAC_BREMS) {
-        const double N = a.C_a * r * r;
-        const double B = A2 * N;
-        const double y = -2.0 * K / (B + sqrt(B * B - 4.0 * b * K));
-        Tp = y * y;
-        Sp = N * y;
-      } else {
-        const double A = A2 * aa;
-        double T = -K / b;
-        if (A > 0.0) T = fmin(T, sqrt(sqrt(-K / A)));
-        bool conv = false;
-        for (int it = 0; it < a.max_iter; ++it) {
-          double T3 = T * T * T;
-          double f = A * T3 * T + b * T + K;
-          double fp = 4.0 * A * T3 + b;
-          double dT = f / fp;
-          T -= dT;
-          if (fabs(dT) <= a.rtol * fabs(T)) {
-            conv = true;
-            break;
-          }
-        }
-        ok = conv;
-        Tp = T;
-        Sp = aa * T * T * T * T;
-      }
-      Ep = Em - Y * (Tp - T0);
-    }
-  }
-  if (!ok) {
-    if (fail) atomicAdd(fail, 1ull);
-    for (int s = 0; s < a.ns; ++s) Iout[(long long)s * a.nc + c] = It[(long long)s * a.nc + c];
-    Tout[c] = T0;
-    if (G)
-      for (int k = 0; k < 4; ++k) G[k * a.nc + c] = 0.0;
-    return;
-  }
-  const double Q = Sp + as * Ep;
-  double g0 = 0.0, g1 = 0.0, g2 = 0.0, g3 = 0.0;
-  for (int s = 0; s < a.ns; ++s) {
-    double nx = dir[s], ny = dir[a.ns + s], nz = dir[2 * a.ns + s];
-    double nb = u0 - (u1 * nx + u2 * ny + u3 * nz);
-    double nb2 = nb * nb, nb4 = nb2 * nb2;
-    double Iin = (double)It[(long long)s * a.nc + c];
-    double den = n0 + nb * ab * h;
-    double cs = n0 / den;
-    double ds = nb * h / (4.0 * kPi * den);
-    double Io = (cs * Iin * nb4 + ds * Q) / nb4;
-    Iout[(long long)s * a.nc + c] = (S)Io;
-    if (G) {
-      double dI = w[s] * ((double)(S)Io - Iin);
-      g0 += dI;
-      g1 += dI * nx;
-      g2 += dI * ny;
-      g3 += dI * nz;
-    }
-  }
-  Tout[c] = Tp;
-  if (G) {
-    G[c] = -g0 / h;
-    G[a.nc + c] = -g1 / h;
-    G[2 * a.nc + c] = -g2 / h;
-    G[3 * a.nc + c] = -g3 / h;
-  }
-}
 
 // ---------------------------------------------------------------------------
 // moments R[k][c] = sum_s I[s][c] W[s][k] (Eq. R) on the FP64 matrix cores:
@@ -448,86 +88,6 @@ hipError_t launch_fluid(rt_ctx* c, const double* u, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_opacity(rt_ctx* c, const double* T_coef, hipStream_t st) {
-  const rt_opacity_desc& o = c->opac;
-  hipLaunchKernelGGL(k_opacity, dim3(blocks_for(c->nc)), dim3(kBlock), 0, st, c->nc, o.model, o.C_a,
-                     o.C_s, c->desc.rho_floor, c->d_rho, T_coef, c->d_ka, c->d_ks, c->d_uhat,
-                     c->d_abar_a, c->d_abar_s, c->d_ahat);
-  return hipGetLastError();
-}
-
-hipError_t launch_faces(rt_ctx* c, double dt, hipStream_t st) {
-  Dims d = dims_of(c);
-  for (int ax = 0; ax < 3; ++ax) {
-    bool per = c->desc.bc_lo[ax] == RT_BC_PERIODIC;
-    const double* v = c->moving ? c->d_v : nullptr;
-    if (c->fp32)
-      hipLaunchKernelGGL(k_faces<float>, dim3(blocks_for(c->nface[ax])), dim3(kBlock), 0, st, d, ax,
-                         per, c->desc.abar, dt, c->desc.limiter, c->d_ahat, v,
-                         (float*)c->d_face[ax], c->nface[ax]);
-    else
-      hipLaunchKernelGGL(k_faces<double>, dim3(blocks_for(c->nface[ax])), dim3(kBlock), 0, st, d,
-                         ax, per, c->desc.abar, dt, c->desc.limiter, c->d_ahat, v,
-                         (double*)c->d_face[ax], c->nface[ax]);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-  }
-  return hipSuccess;
-}
-
-hipError_t launch_transport(rt_ctx* c, const void* I_flux, const void* I_base, void* I_out,
-                            double h, hipStream_t st) {
-  TransportArgs a;
-  a.d = dims_of(c);
-  for (int ax = 0; ax < 3; ++ax) {
-    a.bc_lo[ax] = c->desc.bc_lo[ax];
-    a.bc_hi[ax] = c->desc.bc_hi[ax];
-    a.inv_dx[ax] = 1.0 / c->dx[ax];
-  }
-  a.h = h;
-  a.limiter = c->desc.limiter;
-  a.chunk = 27;
-  dim3 grid(blocks_for(c->nc), (unsigned)((c->ns + a.chunk - 1) / a.chunk));
-  if (c->fp32)
-    hipLaunchKernelGGL((k_transport<float, float>), grid, dim3(kBlock), 0, st, a, (const float*)I_flux,
-                       (const float*)I_base, (float*)I_out, (const float*)c->d_face[0],
-                       (const float*)c->d_face[1], (const float*)c->d_face[2], c->d_dir_f);
-  else
-    hipLaunchKernelGGL((k_transport<double, double>), grid, dim3(kBlock), 0, st, a,
-                       (const double*)I_flux, (const double*)I_base, (double*)I_out,
-                       (const double*)c->d_face[0], (const double*)c->d_face[1],
-                       (const double*)c->d_face[2], c->d_dir);
-  return hipGetLastError();
-}
-
-hipError_t launch_source(rt_ctx* c, const void* I_til, void* I_out, const double* T_start,
-                         const double* T_coef, double* T_out, double h, double* G,
-                         hipStream_t st) {
-  (void)T_coef;  // opacities at T_coef were computed by launch_opacity
-  SourceArgs a;
-  a.nc = c->nc;
-  a.ns = c->ns;
-  a.model = c->opac.model;
-  a.gamma = c->opac.gamma;
-  a.C_a = c->opac.C_a;
-  a.rho_floor = c->desc.rho_floor;
-  a.h = h;
-  a.max_iter = c->opac.newton_max_iter;
-  a.rtol = c->opac.newton_rtol;
-  a.moving = c->moving ? 1 : 0;
-  if (c->fp32)
-    hipLaunchKernelGGL(k_source<float>, dim3(blocks_for(c->nc)), dim3(kBlock), 0, st, a,
-                       (const float*)I_til, (float*)I_out, T_start, T_coef, T_out, c->d_rho,
-                       c->d_uhat, c->d_abar_a, c->d_abar_s, c->d_j, c->d_dir, c->d_w, G,
-                       c->d_count);
-  else
-    hipLaunchKernelGGL(k_source<double>, dim3(blocks_for(c->nc)), dim3(kBlock), 0, st, a,
-                       (const double*)I_til, (double*)I_out, T_start, T_coef, T_out, c->d_rho,
-                       c->d_uhat, c->d_abar_a, c->d_abar_s, c->d_j, c->d_dir, c->d_w, G,
-                       c->d_count);
-  return hipGetLastError();
-}
-
 hipError_t launch_moments(rt_ctx* c, const void* I, double* R, double* J, hipStream_t st) {
   long long waves = (c->nc + 63) / 64;
   unsigned blocks = (unsigned)((waves * 64 + kBlock - 1) / kBlock);
@@ -551,9 +111,5 @@ hipError_t launch_nonfinite(rt_ctx* c, const void* I, const double* T, hipStream
   return hipGetLastError();
 }
 
-hipError_t launch_adjoint_step(rt_ctx*, const void*, double, const void*, void*, double*, double*,
-                               hipStream_t) {
-  return hipErrorNotSupported;
-}
 
 }  // namespace rt

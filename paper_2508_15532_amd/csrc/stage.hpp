@@ -1,0 +1,58 @@
+// Arguments of the fused stage kernel and the materialisation pass.
+#pragma once
+#include <hip/hip_runtime_api.h>
+
+struct rt_ctx;
+
+namespace rt {
+
+struct StageArgs {
+  int n1, n2, n3;
+  long long nc;
+  int ns;
+  int bc_lo[3], bc_hi[3];
+  double inv_dx[3];
+  double h;     // length of this stage's transport and interaction step
+  double dt;    // full step (enters tau)
+  double abar;
+  int limiter;
+  int model;
+  double gamma, C_a, C_s, rho_floor;
+  int max_iter;
+  double rtol;
+  double W0;        // sum of the quadrature weights
+  double Wsum[10];  // sum_s w_s n^a n^b (moments of a unit isotropic field)
+  int tiles_x, tiles_y, tiles_z, ntiles, tiles_per_xcd;
+};
+
+struct StagePtrs {
+  const void* Iflux_v;
+  const double* mapF;   // lazy map (alpha, beta) of Iflux, [2][nc]; NULL = identity
+  const void* Ibase_v;  // stage 2: intensity of the step start (centre only)
+  const double* mapB;   // its lazy map; NULL = identity
+  void* Iout_v;         // transported intensity I~ (may alias Ibase)
+  double* mapO;         // out: (alpha, beta) at rest; (Q, abar, use) with a moving fluid
+  const double* Tstart;
+  const double* Tcoef;
+  double* Tout;
+  const double* rho;
+  const double* ka;
+  const double* ks;
+  const double* jv;
+  const double* uhat;
+  const double* vel;
+  const void* dirF_v;   // [3][ns] directions in the transport type
+  const double* dirD;   // [3][ns] directions in double
+  const double* w;      // [ns]
+  const double* W16;    // [ns][16] moment weights
+  double* Rout;         // stage 2 at rest: moments of the new intensity (nullable)
+  double* Gout;         // stage 2 at rest: 4-force (nullable)
+  unsigned long long* fail;
+};
+
+hipError_t launch_stage(rt_ctx* c, const StageArgs& a, const StagePtrs& p, bool stage2,
+                        hipStream_t st);
+hipError_t launch_materialize(rt_ctx* c, void* I, const double* map, double h, double* R,
+                              double* G, hipStream_t st);
+
+}  // namespace rt

@@ -112,3 +112,43 @@ def patch(field, center, radius):
 
 __all__ = ["W", "gpu_context", "gpu_initial", "gpu_run", "oracle_run", "rel_l2", "rel_max",
            "moments_error", "J_of", "moving_fluid", "patch"]
+
+
+def oracle_grad(wl, steps, I0, weights, limiter=0):
+    """Reference gradient by torch autograd through the FP64 oracle:
+    L = sum(weights * I_N); returns (dL/dI0, dL/dkappa_a, dL/dj)."""
+    from oracle import step as st
+    from oracle.setup import build_flat
+    pb, _, T = build_flat(wl, limiter=limiter)
+    ka = pb.kappa_a.clone().requires_grad_(True)
+    jj = pb.j.clone().requires_grad_(True)
+    pb.kappa_a, pb.j = ka, jj
+    I = torch.as_tensor(I0, dtype=F64).reshape((pb.geo.grid.ns,) + tuple(wl["n"])).clone()
+    I.requires_grad_(True)
+    X = I
+    for _ in range(steps):
+        X, T = st.step(pb, X, T, wl["dt"])
+    L = (torch.as_tensor(weights, dtype=F64).reshape(X.shape) * X).sum()
+    gI, gk, gj = torch.autograd.grad(L, [I, ka, jj])
+    return gI, gk, gj
+
+
+def gpu_grad(wl, steps, I0, weights, precision="fp64", limiter="mc"):
+    """dL/dI0, dL/dkappa_a, dL/dj from the HIP adjoint, for L = sum(weights * I_N)."""
+    ctx = gpu_context(wl, precision, limiter)
+    I, T = gpu_initial(ctx, wl, I0)
+    states = []
+    for _ in range(steps):
+        states.append(I.clone())
+        ctx.step(I, T, wl["dt"], 1)
+    g = torch.as_tensor(np.ascontiguousarray(weights), dtype=F64).reshape(ctx.ns, -1)
+    g = g.to(ctx.intensity_dtype).cuda().contiguous()
+    gk = torch.zeros(ctx.nc, dtype=F64, device="cuda")
+    gj = torch.zeros(ctx.nc, dtype=F64, device="cuda")
+    for I_k in reversed(states):
+        g = ctx.step_adjoint(I_k, T, wl["dt"], g, g, g_kappa_a=gk, g_j=gj)
+    torch.cuda.synchronize()
+    shape = tuple(wl["n"])
+    out = (g.double().cpu().reshape((ctx.ns,) + shape), gk.cpu().reshape(shape), gj.cpu().reshape(shape))
+    ctx.close()
+    return out

@@ -40,7 +40,7 @@ def test_null_arguments_are_rejected_without_device_work():
     assert ctx.value is None
     assert b"NULL" in lib.rt_last_error()
     assert lib.rt_set_metric(None, 0, 1.0, 0.0, 0.4, None) == N.RT_E_ARG
-    assert lib.rt_step(None, None, None, 0.1, 1, None, None) == N.RT_E_ARG
+    assert lib.rt_step(None, None, None, 0.1, 1, None, None, None) == N.RT_E_ARG
     assert lib.rt_moments(None, None, None, None, 0, None) == N.RT_E_ARG
     assert lib.rt_step_adjoint(None, None, None, 0.1, None, None, None, None, None) == N.RT_E_ARG
     lib.rt_destroy(None)

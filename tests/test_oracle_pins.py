@@ -560,3 +560,39 @@ def test_force_at_rest_equals_gas_heating():
     In, Tn, G = st.step(pb, I, T, 0.4, want_G=True)
     Y = pb.rho / (pb.gamma - 1)
     assert torch.allclose(G[0] * 0.4, Y * (Tn - T), rtol=1e-12, atol=1e-14)
+
+
+# --------------------------------------------------------------------------
+# P12  reference gradient (autograd through the oracle) against central FD
+# --------------------------------------------------------------------------
+def test_oracle_reference_gradient_matches_fd():
+    """The oracle's reference gradient (torch autograd through the FP64 step,
+    fixed emissivity, zero-incoming box with scattering) agrees with FP64
+    central differences to O(h^2)."""
+    import sys
+    sys.path.insert(0, os.path.dirname(__file__))
+    from runners import oracle_grad, oracle_run
+    n = (4, 3, 5)
+    rng = np.random.default_rng(0)
+    wl = W.adjoint_flat(n=n, generation=1, seed=3)
+    wl["kappa_s"] = rng.uniform(0, 0.5, n)
+    I0 = W.random_intensity(42, n, 1, 0, 0.3)
+    wts = rng.uniform(-1, 1, (42,) + n)
+    gI, gk, gj = oracle_grad(wl, 2, I0, wts)
+
+    def loss(wl2, I=I0):
+        return float((torch.tensor(wts) * oracle_run(wl2, 2, I0=I)["I"]).sum())
+
+    h = 1e-6
+    for c in [(1, 2, 3), (3, 0, 0), (0, 1, 4)]:
+        for key, g in (("kappa_a", gk), ("j", gj)):
+            ap, am = wl[key].copy(), wl[key].copy()
+            ap[c] += h
+            am[c] -= h
+            fd = (loss(dict(wl, **{key: ap})) - loss(dict(wl, **{key: am}))) / (2 * h)
+            assert abs(float(g[c]) - fd) < 1e-6 * max(1.0, abs(fd)), (key, c)
+    # the step is piecewise linear in I: dL/dI0 matches a directional difference
+    v = rng.uniform(-1, 1, I0.shape)
+    eps = 1e-7
+    fd = (loss(wl, I0 + eps * v) - loss(wl, I0 - eps * v)) / (2 * eps)
+    assert abs(float((gI * torch.tensor(v)).sum()) - fd) < 1e-6 * max(1.0, abs(fd))
