@@ -41,3 +41,23 @@ def build_flat(wl, grid=None, limiter=tr.LIM_MC):
     I0 = _t(wl["I0_iso"]).unsqueeze(0).expand((grid.ns,) + shape).clone()
     T0 = _t(wl["T"]).clone()
     return pb, I0, T0
+
+
+def build_ks(wl, grid=None, limiter=tr.LIM_MC, fd_h=1e-4):
+    """Problem on the Kerr-Schild (ln r, theta, phi) mesh; returns (pb, I0, T0, dt_max)."""
+    from .kerr import KerrSchildLogR
+    grid = grid or GeodesicGrid(wl["generation"], wl["weights"])
+    geo = KerrSchildLogR(wl["n"], wl["xlo"], wl["xhi"], grid, wl["a"], wl.get("M", 1.0), fd_h)
+    shape = tuple(wl["n"])
+    u = np.asarray(wl["u"], dtype=np.float64)
+    u_hat = geo.u_hat(u)
+    v = torch.as_tensor(u[1:] / u[0])
+    bc_lo = tuple(BC[b] for b in wl["bc"])
+    bc_hi = tuple(BC[b] for b in wl.get("bc_hi", wl["bc"]))
+    pb = Problem(geo=geo, rho=_t(wl["rho"]), u_hat=u_hat, v=v, model=MODEL[wl["model"]],
+                 gamma=wl["gamma"], kappa_a=_t(wl.get("kappa_a")), kappa_s=_t(wl.get("kappa_s")),
+                 j=_t(wl.get("j")), C_a=wl.get("C_a", 1.0), C_s=wl.get("C_s", 1.0),
+                 bc_lo=bc_lo, bc_hi=bc_hi, limiter=limiter, n0_cut=wl.get("n0_cut"),
+                 angular=geo.angular, pole_rows=wl.get("pole_rows", 0))
+    I0 = _t(wl["I0_iso"]).unsqueeze(0).expand((grid.ns,) + shape).clone()
+    return pb, I0, _t(wl["T"]).clone(), geo.dt_max(wl.get("cfl", 0.4))

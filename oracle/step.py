@@ -48,6 +48,7 @@ class Problem:
     limiter: int = tr.LIM_MC
     n0_cut: float = None
     angular: object = None                  # callable I -> angular flux divergence (curved)
+    pole_rows: int = 0                      # rows next to each theta boundary zeroed (curved)
     newton_max_iter: int = 50
     newton_rtol: float = 1e-14
     failed: list = field(default_factory=list)
@@ -84,6 +85,12 @@ def stage(pb, I_flux, I_base, h, dt, T_start, T_coef):
     It = tr.transport(I_flux, I_base, h, dt, pb.geo, ah, pb.v, pb.abar, pb.bc_lo, pb.bc_hi,
                       pb.limiter, angular=pb.angular, n0_cut=pb.n0_cut)
     Iout, Tout = source(pb, It, h, T_start, T_coef)
+    if pb.pole_rows:
+        # intensity zeroed in the rows next to each pole (torus setup of Sec. 5)
+        k = pb.pole_rows
+        Iout = Iout.clone()
+        Iout[:, :, :k] = 0.0
+        Iout[:, :, -k:] = 0.0
     return Iout, Tout, It
 
 

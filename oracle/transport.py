@@ -123,6 +123,10 @@ def spatial_divergence(I, geo, alpha_hat, v, dt, abar, bc_lo, bc_hi, limiter):
         vL = vp[..., 1:n + 2] + 0.5 * Dv[..., 0:n + 1]
         vR = vp[..., 2:n + 3] - 0.5 * Dv[..., 1:n + 2]
         F = face_fluxes(P, nu, nl0, nu0, tau, vL, vR, limiter)
+        ok = geo.face_sign_ok(a, bc_lo[a] == PERIODIC) if hasattr(geo, "face_sign_ok") else None
+        if ok is not None:
+            # no flux between cells where n_0 changes sign (Sec. 3.5)
+            F = torch.where(ok.movedim(1 + a, -1), F, torch.zeros_like(F))
         AF = dA * F
         div = div + (AF[..., 1:] - AF[..., :-1]).movedim(-1, 1 + a)
     return div / geo.dV()

@@ -105,3 +105,58 @@ def random_intensity(ns, shape, seed, lo=0.0, hi=1.0):
     """Anisotropic positive intensity field [ns, *shape] for kernel-level parity."""
     rng = np.random.default_rng(seed)
     return rng.uniform(lo, hi, size=(ns,) + tuple(shape))
+
+
+def _ks_equatorial_block(r, th, a):
+    """g_tt, g_tph, g_phph of the Kerr-Schild metric (M = 1); input preparation
+    for the fluid 4-velocity only."""
+    Sig = r * r + a * a * np.cos(th) ** 2
+    z = 2.0 * r / Sig
+    s2 = np.sin(th) ** 2
+    return -(1.0 - z), -z * a * s2, s2 * (Sig + a * a * (1.0 + z) * s2)
+
+
+def torus_ks(n=(256, 128, 64), a=0.9, generation=2, sigma_ln=None, scattering=False, seed=None):
+    """Synthetic torus in Kerr-Schild coordinates (x1 = ln r, theta, phi), r in [1.5, 50]:
+    rho = exp(-(r-12)^2/(2*3^2) - (theta-pi/2)^2/(2*0.3^2)) (times a lognormal field
+    when sigma_ln is given); circular Keplerian flow u = u^t (1, 0, 0, Omega),
+    Omega = 1/(r^1.5 + a), where r >= r_isco(a) and the orbit is timelike, else
+    the normal observer; T0 = 1; alpha^a = rho^2 T^-3.5 (Method 2); alpha^s = rho
+    if scattering; I0 = 0; r: outflow inside, zero-incoming outside; theta:
+    outflow; phi periodic; rows next to the poles zeroed."""
+    rng = rng_for(5 if sigma_ln else 2, seed)
+    shape = tuple(int(v) for v in n)
+    xlo = (math.log(1.5), 0.0, 0.0)
+    xhi = (math.log(50.0), math.pi, 2.0 * math.pi)
+    x1 = xlo[0] + (np.arange(shape[0]) + 0.5) * (xhi[0] - xlo[0]) / shape[0]
+    th = xlo[1] + (np.arange(shape[1]) + 0.5) * (xhi[1] - xlo[1]) / shape[1]
+    r = np.exp(x1)[:, None, None] * np.ones(shape)
+    TH = th[None, :, None] * np.ones(shape)
+    rho = np.exp(-(r - 12.0) ** 2 / 18.0 - (TH - math.pi / 2) ** 2 / (2 * 0.09))
+    if sigma_ln:
+        rho = rho * lognormal(shape, sigma_ln, rng)
+    # ISCO radius of a prograde orbit (Bardeen, Press & Teukolsky 1972)
+    z1 = 1 + (1 - a * a) ** (1 / 3) * ((1 + a) ** (1 / 3) + (1 - a) ** (1 / 3))
+    z2 = math.sqrt(3 * a * a + z1 * z1)
+    r_isco = 3 + z2 - math.sqrt((3 - z1) * (3 + z1 + 2 * z2))
+    Om = 1.0 / (r ** 1.5 + a)
+    gtt, gtp, gpp = _ks_equatorial_block(r, TH, a)
+    norm = gtt + 2 * gtp * Om + gpp * Om * Om
+    kep = (r >= r_isco) & (norm < 0)
+    u = np.zeros((4,) + shape)
+    ut = np.where(kep, 1.0 / np.sqrt(np.where(kep, -norm, 1.0)), 0.0)
+    # normal observer: u = (1/alpha, -beta^i/alpha), alpha = 1/sqrt(1+z),
+    # beta^r = z/(1+z); in x1 = ln r the radial component is divided by r
+    Sig = r * r + a * a * np.cos(TH) ** 2
+    zz = 2.0 * r / Sig
+    u[0] = np.where(kep, ut, np.sqrt(1 + zz))
+    u[1] = np.where(kep, 0.0, -zz / (1 + zz) * np.sqrt(1 + zz) / r)
+    u[3] = np.where(kep, ut * Om, 0.0)
+    return dict(
+        name="torus_ks", n=shape, xlo=xlo, xhi=xhi, coords="logr_theta_phi", metric="kerr_schild",
+        a=a, M=1.0, generation=generation, weights="voronoi",
+        bc=("outflow", "outflow", "periodic"), bc_hi=("zero_incoming", "outflow", "periodic"),
+        model="brems", gamma=5.0 / 3.0, C_a=1.0, C_s=1.0 if scattering else 0.0,
+        rho=rho, T=np.ones(shape), kappa_a=None, kappa_s=None, j=None, u=u,
+        I0_iso=np.zeros(shape), cfl=0.4, steps=50, pole_rows=4, n0_cut=0.1,
+    )
