@@ -181,7 +181,7 @@ rt_status rt_set_debug(rt_ctx* ctx, int flags);
    (counts[k]) and their summed duration in milliseconds (ms[k]) since the
    previous call, then starts a new tally.  Either output may be NULL. */
 enum { RT_K_STAGE1 = 0, RT_K_STAGE2, RT_K_MATERIALIZE, RT_K_MOMENTS, RT_K_ADJOINT,
-       RT_NKERNELS };
+       RT_K_ANGULAR, RT_NKERNELS };
 rt_status rt_kernel_times(rt_ctx* ctx, int* counts, double* ms);
 
 /* Number of interaction failures counted since the last call (debug mode). */

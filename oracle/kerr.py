@@ -255,3 +255,18 @@ class KerrSchildLogR:
         div = div.index_add(0, es, F)
         div = div.index_add(0, et, -F)
         return div / w
+
+
+def coordinate_moments(R_hat, e):
+    """R^(mu nu) = e^mu_a e^nu_b R-hat^(ab) (Eq. R in the coordinate frame).
+    R_hat [10, N1, N2, N3] in the order 00,01,02,03,11,12,13,22,23,33; e the
+    tetrad e^mu_a [N1, N2, 4, 4] (phi-independent).  Same storage order out."""
+    from .step import SYM10
+    R_hat = torch.as_tensor(R_hat, dtype=F64)
+    full = torch.zeros((4, 4) + tuple(R_hat.shape[1:]), dtype=F64)
+    for k, (p, q) in enumerate(SYM10):
+        full[p, q] = R_hat[k]
+        full[q, p] = R_hat[k]
+    E = torch.as_tensor(e, dtype=F64)                                   # [N1, N2, mu, a]
+    Rc = torch.einsum("ijma,abijk,ijnb->mnijk", E, full, E)
+    return torch.stack([Rc[p, q] for p, q in SYM10])

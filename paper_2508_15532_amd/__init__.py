@@ -61,7 +61,7 @@ class RTContext:
 
     def __init__(self, n, xlo, xhi, generation, *, weights="voronoi", precision="fp64",
                  bc=("periodic",) * 3, bc_hi=None, limiter="mc", abar=1.0, rho_floor=5e-4,
-                 n0_cut=0.1, coords="cart", pole_zero_rows=4):
+                 n0_cut=0.1, coords="cart", pole_zero_rows=None):
         self._lib = N.load()
         d = N.GridDesc()
         bc_hi = bc if bc_hi is None else bc_hi
@@ -77,6 +77,8 @@ class RTContext:
         d.precision = _PREC[precision]
         d.limiter = {"mc": N.RT_LIM_MC, "minmod": N.RT_LIM_MINMOD}[limiter]
         d.abar, d.rho_floor, d.n0_cut = float(abar), float(rho_floor), float(n0_cut)
+        if pole_zero_rows is None:
+            pole_zero_rows = 4 if coords == "logr_theta_phi" else 0
         d.pole_zero_rows = int(pole_zero_rows)
         ctx = C.c_void_p()
         N.check(self._lib.rt_init_grid(C.byref(d), C.byref(ctx)))

@@ -21,7 +21,7 @@ RT_LIM_MC, RT_LIM_MINMOD = 0, 1
 RT_FLAT, RT_KERR_SCHILD = 0, 1
 RT_OPAC_KIRCHHOFF_CONST, RT_OPAC_BREMS, RT_OPAC_FIXED_EMISSIVITY = 0, 1, 2
 RT_TETRAD, RT_COORD = 0, 1
-KERNELS = ["stage1", "stage2", "materialize", "moments", "adjoint"]
+KERNELS = ["stage1", "stage2", "materialize", "moments", "adjoint", "angular"]
 
 EXPORTED = ["rt_init_grid", "rt_geodesic_grid", "rt_grid_info", "rt_set_metric", "rt_set_opacities", "rt_step",
             "rt_moments", "rt_step_adjoint", "rt_set_debug", "rt_kernel_times", "rt_newton_failures",

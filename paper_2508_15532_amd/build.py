@@ -18,7 +18,7 @@ COMMON = ["-O3", "-fPIC", "-std=c++17", f"--offload-arch={ARCH}",
           # packed FP32 VALU ops stay disabled (hand-checked scalar/float2 code only)
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-I", os.path.join(ROOT, "include"), "-Wall", "-Wno-unused-result"]
-SOURCES = ["grid.cpp", "api.cpp", "kernels.hip", "stage.hip", "adjoint.hip"]
+SOURCES = ["grid.cpp", "kerr.cpp", "api.cpp", "kernels.hip", "stage.hip", "angular.hip", "adjoint.hip"]
 
 
 def hipcc():

@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "ctx.hpp"
+#include "kerr.hpp"
 #include "stage.hpp"
 
 namespace rt {
@@ -95,6 +96,67 @@ hipError_t timed(rt_ctx* c, int kind, hipStream_t st, F&& launch) {
 }  // namespace
 }  // namespace rt
 
+namespace rt {
+namespace {
+// host FP64 vector -> device array of the transport type
+rt_status upload_as(rt_ctx* c, void** dst, const std::vector<double>& v) {
+  rt_status st = alloc((char**)dst, v.size() * c->elem);
+  if (st) return st;
+  if (c->fp32) {
+    std::vector<float> f(v.begin(), v.end());
+    RT_HIP(hipMemcpy(*dst, f.data(), f.size() * 4, hipMemcpyHostToDevice));
+  } else {
+    RT_HIP(hipMemcpy(*dst, v.data(), v.size() * 8, hipMemcpyHostToDevice));
+  }
+  return RT_OK;
+}
+
+template <typename T>
+rt_status upload(T** dst, const std::vector<T>& v) {
+  rt_status st = alloc(dst, v.size() * sizeof(T));
+  if (st) return st;
+  RT_HIP(hipMemcpy(*dst, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+  return RT_OK;
+}
+
+rt_status set_kerr_schild(rt_ctx* c, double M, double a, double cfl) {
+  KsTables T;
+  try {
+    T = build_ks_tables(c->grid, c->desc.n, c->desc.xlo, c->desc.xhi, a, M, c->desc.n0_cut, cfl, 1e-4);
+  } catch (const std::bad_alloc&) {
+    return fail(RT_E_NOMEM, "rt_set_metric: host allocation failed");
+  } catch (const std::exception& e) {
+    return fail(RT_E_ARG, std::string("rt_set_metric: ") + e.what());
+  }
+  // angular kernel: the largest run of phi cells whose directions fit 64 KiB of LDS
+  int cw = 64;
+  while (cw > 1 && (size_t)c->ns * cw * c->elem > 65536) cw /= 2;
+  if ((size_t)c->ns * cw * c->elem > 65536)
+    return fail(RT_E_ARG, "rt_set_metric: too many directions for the curved FP64 form");
+  c->ks_cw = cw;
+  c->ks_ne = T.ne;
+  c->ks_zin_stride = T.zin_stride;
+  std::vector<int> inc(T.inc_off.begin(), T.inc_off.end());
+  for (size_t k = 0; k < T.inc_edge.size(); ++k) {
+    inc.push_back(T.inc_edge[k]);
+    inc.push_back(T.inc_other[k]);
+    inc.push_back(T.inc_side[k]);
+  }
+  rt_status st = RT_OK;
+  if ((st = upload_as(c, &c->d_rec_r, T.fr)) || (st = upload_as(c, &c->d_rec_t, T.ft)) ||
+      (st = upload_as(c, &c->d_rec_p, T.fp)) || (st = upload_as(c, &c->d_ve, T.ve)) ||
+      (st = upload_as(c, &c->d_dV, T.dV)) || (st = upload(&c->d_zin, T.zin)) ||
+      (st = upload(&c->d_nu0, T.nu0)) || (st = upload(&c->d_e, T.e)) ||
+      (st = upload(&c->d_einv, T.einv)) || (st = upload(&c->d_inc, inc)) ||
+      (st = alloc((char**)&c->d_angD, (size_t)c->ns * c->nc * c->elem)))
+    return st;
+  c->dt_max = T.dt_max;
+  c->curved = true;
+  return RT_OK;
+}
+}  // namespace
+}  // namespace rt
+
 using namespace rt;
 
 extern "C" {
@@ -115,7 +177,12 @@ rt_status rt_init_grid(const rt_grid_desc* d, rt_ctx** out) {
     if ((d->bc_lo[a] == RT_BC_PERIODIC) != (d->bc_hi[a] == RT_BC_PERIODIC))
       return fail(RT_E_ARG, "rt_init_grid: periodic must be set on both sides of an axis");
   }
-  if (d->coords != RT_CART) return fail(RT_E_ARG, "rt_init_grid: only RT_CART coordinates are built");
+  if (d->coords != RT_CART && d->coords != RT_LOGR_THETA_PHI) return fail(RT_E_ARG, "rt_init_grid: bad coords");
+  if (d->pole_zero_rows < 0 || 2 * d->pole_zero_rows > d->n[1])
+    return fail(RT_E_ARG, "rt_init_grid: pole_zero_rows must be in 0..n[1]/2");
+  if (d->coords == RT_CART && d->pole_zero_rows != 0)
+    return fail(RT_E_ARG, "rt_init_grid: pole_zero_rows needs RT_LOGR_THETA_PHI");
+  if (!(d->n0_cut >= 0.0)) return fail(RT_E_ARG, "rt_init_grid: n0_cut must be >= 0");
   if (d->generation < 0 || d->generation > 5) return fail(RT_E_ARG, "rt_init_grid: generation in 0..5");
   if (d->weights != RT_W_VORONOI && d->weights != RT_W_EQUAL) return fail(RT_E_ARG, "rt_init_grid: bad weights");
   if (d->precision != RT_FP64 && d->precision != RT_FP32_TRANSPORT)
@@ -222,20 +289,29 @@ rt_status rt_grid_info(const rt_ctx* c, int* n_dirs, double* dirs_host, double* 
 }
 
 rt_status rt_set_metric(rt_ctx* c, int kind, double M, double a, double cfl, double* dt_max_out) {
-  (void)M;
-  (void)a;
   if (!c) return fail(RT_E_ARG, "rt_set_metric: ctx is NULL");
   if (!(cfl > 0.0)) return fail(RT_E_ARG, "rt_set_metric: cfl must be > 0");
-  if (kind != RT_FLAT) return fail(RT_E_ARG, "rt_set_metric: only RT_FLAT is built for RT_CART");
+  if (kind != RT_FLAT && kind != RT_KERR_SCHILD) return fail(RT_E_ARG, "rt_set_metric: bad kind");
+  if (kind == RT_FLAT && c->desc.coords != RT_CART)
+    return fail(RT_E_ARG, "rt_set_metric: RT_FLAT needs RT_CART coordinates");
+  if (kind == RT_KERR_SCHILD && c->desc.coords != RT_LOGR_THETA_PHI)
+    return fail(RT_E_ARG, "rt_set_metric: RT_KERR_SCHILD needs RT_LOGR_THETA_PHI coordinates");
+  if (kind == RT_KERR_SCHILD && (!(M >= 0.0) || !(std::fabs(a) <= M || M == 0.0) || (M == 0.0 && a != 0.0)))
+    return fail(RT_E_ARG, "rt_set_metric: need M >= 0 and |a| <= M");
+  if (c->metric_set) return fail(RT_E_STATE, "rt_set_metric: the metric is already set");
   rt_status st = use_device(c);
   if (st) return st;
   c->metric_kind = kind;
-  double vmax[3] = {0, 0, 0};
-  for (int s = 0; s < c->ns; ++s)
-    for (int k = 0; k < 3; ++k) vmax[k] = std::max(vmax[k], std::fabs(c->grid.dir[s][k]));
-  double dtm = INFINITY;
-  for (int k = 0; k < 3; ++k) dtm = std::min(dtm, c->dx[k] / vmax[k]);
-  c->dt_max = cfl * dtm;
+  if (kind == RT_FLAT) {
+    double vmax[3] = {0, 0, 0};
+    for (int s = 0; s < c->ns; ++s)
+      for (int k = 0; k < 3; ++k) vmax[k] = std::max(vmax[k], std::fabs(c->grid.dir[s][k]));
+    double dtm = INFINITY;
+    for (int k = 0; k < 3; ++k) dtm = std::min(dtm, c->dx[k] / vmax[k]);
+    c->dt_max = cfl * dtm;
+  } else if ((st = set_kerr_schild(c, M, a, cfl))) {
+    return st;
+  }
   // per-stage scratch: one intensity copy (the half-step state) and two lazy maps
   const size_t nc = (size_t)c->nc, ns = (size_t)c->ns;
   if ((st = alloc(&c->d_Tstar, nc * 8)) || (st = alloc(&c->d_mapA, 3 * nc * 8)) ||
@@ -264,8 +340,9 @@ rt_status rt_set_opacities(rt_ctx* c, const rt_opacity_desc* o, hipStream_t stre
   if ((st = alloc(&c->d_rho, nb)) || (st = alloc(&c->d_uhat, 4 * nb)) || (st = alloc(&c->d_v, 3 * nb)))
     return st;
   RT_HIP(hipMemcpyAsync(c->d_rho, o->rho, nb, hipMemcpyDeviceToDevice, stream));
-  // flat metric, identity tetrad: u-hat = u; v^a = u^a / u^0 for the advection term
-  c->moving = o->u != nullptr;
+  // u-hat^a = e^a_mu u^mu (identity when flat); v^a = u^a / u^0 for the advection
+  // term.  The curved geometry always takes the direction-dependent map.
+  c->moving = o->u != nullptr || c->curved;
   RT_HIP(launch_fluid(c, o->u, stream));
   auto copy_opt = [&](double** dst, const double* src) -> rt_status {
     if (!src) {
@@ -321,6 +398,9 @@ rt_status rt_step(rt_ctx* c, void* I, double* T, double dt, int nsteps, double* 
   a.rtol = c->opac.newton_rtol;
   a.W0 = c->W0;
   for (int k = 0; k < 10; ++k) a.Wsum[k] = c->Wsum[k];
+  a.curved = c->curved ? 1 : 0;
+  a.zin_stride = c->ks_zin_stride;
+  a.pole_rows = c->desc.pole_zero_rows;
   StagePtrs p{};
   p.rho = c->d_rho;
   p.ka = c->d_ka;
@@ -333,6 +413,14 @@ rt_status rt_step(rt_ctx* c, void* I, double* T, double dt, int nsteps, double* 
   p.w = c->d_w;
   p.W16 = c->d_W16;
   p.fail = c->d_count;
+  if (c->curved) {
+    p.rec_r_v = c->d_rec_r;
+    p.rec_t_v = c->d_rec_t;
+    p.rec_p_v = c->d_rec_p;
+    p.zin = c->d_zin;
+    p.angD_v = c->d_angD;
+    p.nu0 = c->d_nu0;
+  }
   const double* mapA = nullptr;  // the caller's I is materialised on entry
   for (int k = 0; k < nsteps; ++k) {
     const bool last = k == nsteps - 1;
@@ -349,6 +437,8 @@ rt_status rt_step(rt_ctx* c, void* I, double* T, double dt, int nsteps, double* 
     p.Tout = c->d_Tstar;
     p.Rout = nullptr;
     p.Gout = nullptr;
+    if (c->curved)
+      RT_HIP(timed(c, RT_K_ANGULAR, stream, [&] { return launch_angular(c, I, stream); }));
     RT_HIP(timed(c, RT_K_STAGE1, stream, [&] { return launch_stage(c, a, p, false, stream); }));
     const double* mapB = c->d_mapB;
     if (c->moving) {
@@ -370,6 +460,8 @@ rt_status rt_step(rt_ctx* c, void* I, double* T, double dt, int nsteps, double* 
     p.Tout = T;
     p.Rout = c->moving ? nullptr : R_out;
     p.Gout = (c->moving || !last) ? nullptr : G_out;
+    if (c->curved)
+      RT_HIP(timed(c, RT_K_ANGULAR, stream, [&] { return launch_angular(c, c->d_Itil, stream); }));
     RT_HIP(timed(c, RT_K_STAGE2, stream, [&] { return launch_stage(c, a, p, true, stream); }));
     if (c->moving) {
       RT_HIP(timed(c, RT_K_MATERIALIZE, stream, [&] {
@@ -408,8 +500,9 @@ rt_status rt_moments(rt_ctx* c, const void* I, double* R, double* J, int frame, 
   if (frame != RT_TETRAD && frame != RT_COORD) return fail(RT_E_ARG, "rt_moments: bad frame");
   rt_status st = use_device(c);
   if (st) return st;
-  // flat metric: the identity tetrad makes both frames coincide
   RT_HIP(timed(c, RT_K_MOMENTS, stream, [&] { return launch_moments(c, I, R, J, stream); }));
+  // flat metric: the identity tetrad makes both frames coincide
+  if (frame == RT_COORD && c->curved) RT_HIP(launch_to_coord(c, R, stream));
   return RT_OK;
 }
 
@@ -420,6 +513,7 @@ rt_status rt_step_adjoint(rt_ctx* c, const void* I_n, const double* T_n, double 
   if (!c->metric_set || !c->opac_set) return fail(RT_E_STATE, "rt_step_adjoint: set metric and opacities first");
   if (c->opac.model != RT_OPAC_FIXED_EMISSIVITY)
     return fail(RT_E_ARG, "rt_step_adjoint: only the FIXED_EMISSIVITY model is differentiated");
+  if (c->curved) return fail(RT_E_ARG, "rt_step_adjoint: only the flat metric is differentiated");
   if (c->moving) return fail(RT_E_ARG, "rt_step_adjoint: fluid must be at rest");
   if (!I_n || !T_n || !gI_np1 || !gI_n) return fail(RT_E_ARG, "rt_step_adjoint: NULL argument");
   if (!aligned(I_n) || !aligned(T_n) || !aligned(gI_np1) || !aligned(gI_n) ||
@@ -502,6 +596,17 @@ void rt_destroy(rt_ctx* c) {
   release(c->d_gD);
   release(c->d_gcell);
   release(c->d_count);
+  release(c->d_rec_r);
+  release(c->d_rec_t);
+  release(c->d_rec_p);
+  release(c->d_zin);
+  release(c->d_ve);
+  release(c->d_dV);
+  release(c->d_nu0);
+  release(c->d_e);
+  release(c->d_einv);
+  release(c->d_inc);
+  release(c->d_angD);
   for (auto& t : c->timed) {
     (void)hipEventDestroy(t.a);
     (void)hipEventDestroy(t.b);

@@ -24,6 +24,20 @@ struct rt_ctx {
   int metric_kind = RT_FLAT;
   double dx[3] = {1, 1, 1};
   double dt_max = 0;
+  // Kerr-Schild tables on the device (curved geometry; NULL when flat)
+  bool curved = false;
+  int ks_ne = 0, ks_zin_stride = 0, ks_cw = 64;
+  void* d_rec_r = nullptr;       // [ns][(N1+1) N2][4] transport type
+  void* d_rec_t = nullptr;       // [ns][N1 (N2+1)][4]
+  void* d_rec_p = nullptr;       // [ns][N1 N2][4]
+  unsigned char* d_zin = nullptr;
+  void* d_ve = nullptr;          // [N1 N2][ne][2] transport type
+  void* d_dV = nullptr;          // [N1 N2] transport type
+  double* d_nu0 = nullptr;       // [N1 N2]
+  double* d_e = nullptr;         // [N1 N2][16] e^mu_a
+  double* d_einv = nullptr;      // [N1 N2][16] e^a_mu
+  int* d_inc = nullptr;          // [ns+1] offsets, then [ninc][3] (edge, other, side)
+  void* d_angD = nullptr;        // [ns][nc] angular divergence scratch
 
   // device grid tables
   double* d_dir = nullptr;    // [3][ns] n-hat components, component-major
@@ -72,6 +86,8 @@ void set_error(const std::string& msg);
 // all launchers enqueue on `st` and return the launch status
 hipError_t launch_fluid(rt_ctx* c, const double* u, hipStream_t st);
 hipError_t launch_moments(rt_ctx* c, const void* I, double* R, double* J, hipStream_t st);
+// R^(ab) (tetrad) -> R^(mu nu) = e^mu_a e^nu_b R^(ab) in place (curved geometry)
+hipError_t launch_to_coord(rt_ctx* c, double* R, hipStream_t st);
 hipError_t launch_nonfinite(rt_ctx* c, const void* I, const double* T, hipStream_t st);
 hipError_t launch_adjoint_step(rt_ctx* c, const void* I_n, const double* T_n, double dt,
                                const void* gI_np1, void* gI_n, double* g_ka, double* g_j,

@@ -68,15 +68,55 @@ __global__ void k_nonfinite(long long n, const S* __restrict__ I, long long nT,
 }
 
 // tetrad-frame fluid velocity (identity tetrad) and coordinate 3-velocity
-__global__ void k_fluid(long long nc, const double* __restrict__ u, double* __restrict__ uhat,
-                        double* __restrict__ v) {
+// Tetrad-frame fluid 4-velocity u-hat^a = e^a_mu u^mu and coordinate
+// 3-velocity v^i = u^i / u^0 per cell.  Flat: identity tetrad.  Curved: einv
+// holds e^a_mu per (r, theta) position (index c / n3); a NULL u means the
+// normal observer, u-hat = (1, 0, 0, 0), u^mu = e^mu_0 (etet per position).
+__global__ void k_fluid(long long nc, int n3, const double* __restrict__ u,
+                        const double* __restrict__ einv, const double* __restrict__ etet,
+                        double* __restrict__ uhat, double* __restrict__ v) {
   long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= nc) return;
   double u4[4] = {1.0, 0.0, 0.0, 0.0};
-  if (u)
+  if (einv && !u) {
+    const double* e = etet + (c / n3) * 16;
+    for (int k = 0; k < 4; ++k) u4[k] = e[k * 4 + 0];
+  } else if (u) {
     for (int k = 0; k < 4; ++k) u4[k] = u[k * nc + c];
-  for (int k = 0; k < 4; ++k) uhat[k * nc + c] = u4[k];
+  }
+  for (int a = 0; a < 4; ++a) {
+    double x = u4[a];
+    if (einv) {
+      const double* L = einv + (c / n3) * 16 + a * 4;
+      x = (u ? L[0] * u4[0] + L[1] * u4[1] + L[2] * u4[2] + L[3] * u4[3] : (a == 0 ? 1.0 : 0.0));
+    }
+    uhat[a * nc + c] = x;
+  }
   for (int k = 0; k < 3; ++k) v[k * nc + c] = u4[k + 1] / u4[0];
+}
+
+// R^(mu nu) = e^mu_a e^nu_b R^(ab) in place, symmetric storage of 10 components
+__global__ void k_to_coord(long long nc, int n3, const double* __restrict__ etet, double* __restrict__ R) {
+  long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= nc) return;
+  const int pa[10] = {0, 0, 0, 0, 1, 1, 1, 2, 2, 3};
+  const int pb[10] = {0, 1, 2, 3, 1, 2, 3, 2, 3, 3};
+  double full[4][4];
+  for (int k = 0; k < 10; ++k) full[pa[k]][pb[k]] = full[pb[k]][pa[k]] = R[k * nc + c];
+  const double* e = etet + (c / n3) * 16;  // e[mu*4 + a]
+  double t[4][4];
+  for (int m = 0; m < 4; ++m)
+    for (int b = 0; b < 4; ++b) {
+      double x = 0.0;
+      for (int a = 0; a < 4; ++a) x += e[m * 4 + a] * full[a][b];
+      t[m][b] = x;
+    }
+  for (int k = 0; k < 10; ++k) {
+    const int m = pa[k], n = pb[k];
+    double x = 0.0;
+    for (int b = 0; b < 4; ++b) x += t[m][b] * e[n * 4 + b];
+    R[k * nc + c] = x;
+  }
 }
 
 inline unsigned blocks_for(long long n) { return (unsigned)((n + kBlock - 1) / kBlock); }
@@ -84,7 +124,13 @@ inline unsigned blocks_for(long long n) { return (unsigned)((n + kBlock - 1) / k
 }  // namespace
 
 hipError_t launch_fluid(rt_ctx* c, const double* u, hipStream_t st) {
-  hipLaunchKernelGGL(k_fluid, dim3(blocks_for(c->nc)), dim3(kBlock), 0, st, c->nc, u, c->d_uhat, c->d_v);
+  hipLaunchKernelGGL(k_fluid, dim3(blocks_for(c->nc)), dim3(kBlock), 0, st, c->nc, c->n[2], u,
+                     c->curved ? c->d_einv : nullptr, c->d_e, c->d_uhat, c->d_v);
+  return hipGetLastError();
+}
+
+hipError_t launch_to_coord(rt_ctx* c, double* R, hipStream_t st) {
+  hipLaunchKernelGGL(k_to_coord, dim3(blocks_for(c->nc)), dim3(kBlock), 0, st, c->nc, c->n[2], c->d_e, R);
   return hipGetLastError();
 }
 

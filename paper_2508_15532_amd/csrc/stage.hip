@@ -183,7 +183,7 @@ __device__ Solve solve_cell(const StageArgs& a, double r, double T0, double aa, 
 // After the last direction each thread solves the temperature equation of its
 // cells and writes the cell's lazy interaction map.
 // ---------------------------------------------------------------------------
-template <typename S, typename F, int TY, int TZ, bool STAGE2, bool MOVING, int LIM>
+template <typename S, typename F, int TY, int TZ, bool STAGE2, bool MOVING, int LIM, bool CURVED>
 __global__ void __launch_bounds__(TX* TY)
 k_stage(StageArgs a, StagePtrs p) {
   constexpr int NT = TX * TY;
@@ -199,6 +199,13 @@ k_stage(StageArgs a, StagePtrs p) {
   constexpr int OFY = JX * NT, OFZ = (JX + JY) * NT;
   __shared__ F reg[2][NJ * NT];
   __shared__ F flx[2][(JX + JY + JZ) * NT];
+  // curved geometry: per-direction face records of the tile, {gP, gN, gA, x},
+  // for the x1 faces ((TZ+1) x TY), theta faces (TZ x (TY+1)) and phi rows /
+  // centres (TZ x TY), staged like the intensity region
+  constexpr int NRR = (TZ + 1) * TY, NRT = TZ * (TY + 1), NRP = TZ * TY;
+  constexpr int NREC = NRR + NRT + NRP;
+  static_assert(!CURVED || NREC * 4 <= NT, "one record word per thread");
+  __shared__ F grec[CURVED ? 2 : 1][CURVED ? NREC * 4 : 1];
 
   // ---- tile of this workgroup (XCD-aware: each XCD gets a contiguous range)
   const int b = blockIdx.x;
@@ -230,11 +237,14 @@ k_stage(StageArgs a, StagePtrs p) {
   unsigned zf[(NJ * 6 + 31) / 32];
 #pragma unroll
   for (int q = 0; q < (NJ * 6 + 31) / 32; ++q) zf[q] = 0;
+  // curved: offset of the slot's boundary face in the incoming flags (-1: none)
+  int zoff[CURVED ? NJ : 1];
 #pragma unroll
   for (int j = 0; j < NJ; ++j) {
     const int k = t + j * NT;
     int gi = -1;
     F ma = F(1), mb = F(0);
+    if (CURVED) zoff[j] = -1;
     if (k < NREG) {
       const int rx = k % RX, ry = (k / RX) % RY, rz = k / (RX * RY);
       const bool hz = rz < 2 || rz >= TZ + 2, hy = ry < 2 || ry >= TY + 2, hx = rx < 2 || rx >= TX + 2;
@@ -247,8 +257,21 @@ k_stage(StageArgs a, StagePtrs p) {
         if (gy >= n2 && a.bc_hi[1] == RT_BC_ZERO_INCOMING) f |= 8u;
         if (gx < 0 && a.bc_lo[2] == RT_BC_ZERO_INCOMING) f |= 16u;
         if (gx >= n3 && a.bc_hi[2] == RT_BC_ZERO_INCOMING) f |= 32u;
-        zf[(j * 6) / 32] |= f << ((j * 6) % 32);
-        if ((j * 6) % 32 > 26) zf[(j * 6) / 32 + 1] |= f >> (32 - (j * 6) % 32);
+        if (CURVED) {
+          // flags of the boundary face of the slot's line; slots outside two
+          // sides at once (tile overhang corners) feed no valid cell and keep -1
+          const int b2 = 2 * n2, b1 = 2 * n2 + n1, bp = 2 * n2 + 2 * n1, np = n1 * n2;
+          const bool iz = gz >= 0 && gz < n1, iy = gy >= 0 && gy < n2, ix = gx >= 0 && gx < n3;
+          zoff[j] = ((f & 1u) && iy && ix) ? gy
+                  : ((f & 2u) && iy && ix) ? n2 + gy
+                  : ((f & 4u) && iz && ix) ? b2 + gz
+                  : ((f & 8u) && iz && ix) ? b1 + gz
+                  : ((f & 16u) && iz && iy) ? bp + gz * n2 + gy
+                  : ((f & 32u) && iz && iy) ? bp + np + gz * n2 + gy : -1;
+        } else {
+          zf[(j * 6) / 32] |= f << ((j * 6) % 32);
+          if ((j * 6) % 32 > 26) zf[(j * 6) / 32 + 1] |= f >> (32 - (j * 6) % 32);
+        }
         gi = (int)gcell(gz, gy, gx);
         if (p.mapF) {
           ma = (F)p.mapF[gi];
@@ -263,6 +286,10 @@ k_stage(StageArgs a, StagePtrs p) {
   bool anyzf = false;
 #pragma unroll
   for (int q = 0; q < (NJ * 6 + 31) / 32; ++q) anyzf |= zf[q] != 0u;
+  if (CURVED) {
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) anyzf |= zoff[j] >= 0;
+  }
   auto slot_flags = [&](int j) -> unsigned {
     const int bit = j * 6, w = bit / 32, o = bit % 32;
     unsigned v = zf[w] >> o;
@@ -319,14 +346,18 @@ k_stage(StageArgs a, StagePtrs p) {
     return true;
   };
   int fr0[JF];  // region index of the cell on the upper side of each face slot (-1: none)
+  int frec[CURVED ? JF : 1];  // curved: record of each face slot
 #pragma unroll
   for (int q = 0; q < JF; ++q) {
     int axis, fz, fy, fx;
     fc[q] = FaceC<F>{F(0), F(0), F(0), F(0)};
     if (MOVING) adL[q] = adR[q] = F(0);
     fr0[q] = ((2 + 0) * RY + 2) * RX + 2;  // any interior word for unused slots
+    if (CURVED) frec[q] = 0;
     if (!face_of(q, axis, fz, fy, fx)) continue;
     fr0[q] = ((fz + 2) * RY + fy + 2) * RX + fx + 2;
+    if (CURVED)
+      frec[q] = axis == 0 ? fz * TY + fy : (axis == 1 ? NRR + fz * (TY + 1) + fy : NRR + NRT + fz * TY + fy);
     const int z = z0 + fz, y = y0 + fy, x = x0 + fx;
     const int dz = axis == 0, dy = axis == 1, dx = axis == 2;
     const double tau =
@@ -347,10 +378,37 @@ k_stage(StageArgs a, StagePtrs p) {
     }
   }
 
+  // ---- curved: the record word this thread stages every direction
+  const F* gsrc = nullptr;
+  long long gstride = 0;
+  if (CURVED && t < NREC * 4) {
+    const int rec = t >> 2, comp = t & 3;
+    if (rec < NRR) {
+      const int i1 = z0 + rec / TY, i2 = y0 + rec % TY;
+      if (i1 <= n1 && i2 < n2) {
+        gsrc = (const F*)p.rec_r_v + ((long long)i1 * n2 + i2) * 4 + comp;
+        gstride = (long long)(n1 + 1) * n2 * 4;
+      }
+    } else if (rec < NRR + NRT) {
+      const int r2 = rec - NRR, i1 = z0 + r2 / (TY + 1), i2 = y0 + r2 % (TY + 1);
+      if (i1 < n1 && i2 <= n2) {
+        gsrc = (const F*)p.rec_t_v + ((long long)i1 * (n2 + 1) + i2) * 4 + comp;
+        gstride = (long long)n1 * (n2 + 1) * 4;
+      }
+    } else {
+      const int r3 = rec - NRR - NRT, i1 = z0 + r3 / TY, i2 = y0 + r3 % TY;
+      if (i1 < n1 && i2 < n2) {
+        gsrc = (const F*)p.rec_p_v + ((long long)i1 * n2 + i2) * 4 + comp;
+        gstride = (long long)n1 * n2 * 4;
+      }
+    }
+  }
+
   // ---- own-cell data used in the direction loop
   F bA[TZ], bB[TZ];                        // lazy map of the stage-2 base intensity
   double u0[TZ], u1[TZ], u2[TZ], u3[TZ];   // moving fluid: tetrad-frame 4-velocity
   double abh[TZ];                          // moving fluid: (alpha^a + alpha^s) h
+  double nu0k[TZ];                         // n^0 = 1/lapse (1 when flat)
 #pragma unroll
   for (int k = 0; k < TZ; ++k) {
     const long long c = own[k];
@@ -369,6 +427,7 @@ k_stage(StageArgs a, StagePtrs p) {
       opac(a, p.rho, p.Tcoef, p.ka, p.ks, c, x1, x2);
       abh[k] = (x1 + x2) * a.h;
     }
+    nu0k[k] = CURVED ? p.nu0[c / n3] : 1.0;
   }
 
   // accumulators: at rest sum w n^a n^b I~ (10, E_- is the first); moving E_-, A1, A2
@@ -386,8 +445,16 @@ k_stage(StageArgs a, StagePtrs p) {
   // prefetch of direction 0
   S pre[NJ];
   S prb[TZ];
+  S pda[CURVED ? TZ : 1];  // curved: angular divergence of the own cells
+  F gpre = F(0);
+  const S* angD = (const S*)p.angD_v;
 #pragma unroll
   for (int j = 0; j < NJ; ++j) pre[j] = Iflux[gidx[j]];
+  if (CURVED) {
+    if (gsrc) gpre = gsrc[0];
+#pragma unroll
+    for (int k = 0; k < TZ; ++k) pda[k] = angD[own[k]];
+  }
   if (STAGE2) {
 #pragma unroll
     for (int k = 0; k < TZ; ++k) prb[k] = Ibase[own[k]];
@@ -403,7 +470,12 @@ k_stage(StageArgs a, StagePtrs p) {
     const unsigned inc = (nz > F(0) ? 1u : 0u) | (nz < F(0) ? 2u : 0u) | (ny > F(0) ? 4u : 0u) |
                          (ny < F(0) ? 8u : 0u) | (nx > F(0) ? 16u : 0u) | (nx < F(0) ? 32u : 0u);
     // 1. stage the region (lazy map applied)
-    if (anyzf) {
+    if (CURVED && anyzf) {
+      const unsigned char* zs = p.zin + (long long)s * a.zin_stride;
+#pragma unroll
+      for (int j = 0; j < NJ; ++j)
+        R[t + j * NT] = (zoff[j] >= 0 && zs[zoff[j]]) ? F(0) : mA[j] * (F)pre[j] + mB[j];
+    } else if (anyzf) {
 #pragma unroll
       for (int j = 0; j < NJ; ++j)
         R[t + j * NT] = (slot_flags(j) & inc) ? F(0) : mA[j] * (F)pre[j] + mB[j];
@@ -416,6 +488,13 @@ k_stage(StageArgs a, StagePtrs p) {
 #pragma unroll
       for (int k = 0; k < TZ; ++k) base[k] = bA[k] * (F)prb[k] + bB[k];
     }
+    F dang[CURVED ? TZ : 1];
+    F* GR = grec[CURVED ? buf : 0];
+    if (CURVED) {
+      if (t < NREC * 4) GR[t] = gpre;
+#pragma unroll
+      for (int k = 0; k < TZ; ++k) dang[k] = (F)pda[k];
+    }
     __syncthreads();
     // prefetch the next direction while this one is computed
     if (s + 1 < ns) {
@@ -426,6 +505,12 @@ k_stage(StageArgs a, StagePtrs p) {
         const S* Ib = Ibase + (long long)(s + 1) * nc;
 #pragma unroll
         for (int k = 0; k < TZ; ++k) prb[k] = Ib[own[k]];
+      }
+      if (CURVED) {
+        if (gsrc) gpre = gsrc[(long long)(s + 1) * gstride];
+        const S* As = angD + (long long)(s + 1) * nc;
+#pragma unroll
+        for (int k = 0; k < TZ; ++k) pda[k] = As[own[k]];
       }
     }
     // 2. face fluxes, each face once; the sign of the direction component is
@@ -456,9 +541,28 @@ k_stage(StageArgs a, StagePtrs p) {
         for (int qq = 0; qq < QN; ++qq) one(Q0 + qq, false);
       }
     };
-    faces(std::integral_constant<int, 2>{}, nx);
-    faces(std::integral_constant<int, 1>{}, ny);
-    faces(std::integral_constant<int, 0>{}, nz);
+    if (CURVED) {
+      // direction components vary with position: both upwind forms, weighted
+      // by the face records (one of gP, gN is zero)
+#pragma unroll
+      for (int q = 0; q < JF; ++q) {
+        const int ST = q < JX ? 1 : (q < JX + JY ? RX : RX * RY);
+        const F* Rq = R + fr0[q];
+        const F vm2 = Rq[-2 * ST], vm1 = Rq[-ST], v0 = Rq[0], vp1 = Rq[ST];
+        const F d0 = vm1 - vm2, d1 = v0 - vm1, d2 = vp1 - v0;
+        const F hL = half_slope<LIM>(d0, d1), hR = half_slope<LIM>(d1, d2);
+        const F* g = GR + frec[q] * 4;
+        const FaceC<F>& c = fc[q];
+        F fl = g[0] * (c.P * vm1 + c.Q * v0 + c.U * hL - c.V * hR) +
+               g[1] * (c.Q * vm1 + c.P * v0 + c.V * hL - c.U * hR);
+        if (MOVING) fl += g[2] * (adL[q] * (vm1 + hL) + adR[q] * (v0 - hR));
+        FL[t + q * NT] = fl;
+      }
+    } else {
+      faces(std::integral_constant<int, 2>{}, nx);
+      faces(std::integral_constant<int, 1>{}, ny);
+      faces(std::integral_constant<int, 0>{}, nz);
+    }
     __syncthreads();
     // 3. divergence, update, interaction sums
     const double ws = p.w[s];
@@ -469,9 +573,18 @@ k_stage(StageArgs a, StagePtrs p) {
       const F fyh = FL[OFY + (k * (TY + 1) + ty + 1) * TX + tx];
       const F fzl = FL[OFZ + (k * TY + ty) * TX + tx];
       const F fzh = FL[OFZ + ((k + 1) * TY + ty) * TX + tx];
-      const F div = (fzh - fzl) * idx0 + (fyh - fyl) * idx1 + (fxh - fxl) * idx2;
       const F bse = STAGE2 ? base[k] : R[((k + 2) * RY + ty + 2) * RX + tx + 2];
-      const F It = bse - h * div;
+      F It;
+      if (CURVED) {
+        // X = n^0 n_0 I updated by the area-weighted face fluxes; x = 1/(dV n^0 n_0),
+        // zero where |n_0| is below the cut (I~ = 0 there)
+        const F x = GR[(NRR + NRT + k * TY + ty) * 4 + 3];
+        const F sum = (fzh - fzl) + (fyh - fyl) + (fxh - fxl);
+        It = (x != F(0) ? bse : F(0)) - h * (x * sum + dang[k]);
+      } else {
+        const F div = (fzh - fzl) * idx0 + (fyh - fyl) * idx1 + (fxh - fxl) * idx2;
+        It = bse - h * div;
+      }
       if (valid[k]) Iout[(long long)s * nc + own[k]] = (S)It;
       // ---- interaction sums (FP64)
       const double Itd = (double)(S)It;
@@ -479,9 +592,9 @@ k_stage(StageArgs a, StagePtrs p) {
         const double nb = u0[k] - (u1[k] * p.dirD[s] + u2[k] * p.dirD[ns + s] + u3[k] * p.dirD[2 * ns + s]);
         const double nb2 = nb * nb;
         const double Ib = Itd * nb2 * nb2, dOb = ws / nb2;
-        const double den = 1.0 + nb * abh[k];
+        const double den = nu0k[k] + nb * abh[k];
         acc[k][0] += Ib * dOb;
-        acc[k][1] += Ib * dOb / den;
+        acc[k][1] += nu0k[k] * Ib * dOb / den;
         acc[k][2] += nb * a.h / (4.0 * kPi * den) * dOb;
       } else if (STAGE2) {
 #pragma unroll
@@ -523,7 +636,10 @@ k_stage(StageArgs a, StagePtrs p) {
       // parameters of the direction-dependent map, applied by the materialisation
       p.mapO[c] = use ? so.Q : 0.0;
       p.mapO[nc + c] = ab;
-      p.mapO[2 * nc + c] = use ? 1.0 : 0.0;
+      // 1: apply the interaction, 0: keep I~, 2: zero (rows next to the axis)
+      const int gyk = (int)((c / n3) % n2);
+      const bool pole = CURVED && (gyk < a.pole_rows || gyk >= n2 - a.pole_rows);
+      p.mapO[2 * nc + c] = pole ? 2.0 : (use ? 1.0 : 0.0);
     } else {
       const double al = use ? 1.0 / (1.0 + ab * a.h) : 1.0;
       const double be = use ? a.h * so.Q / (4.0 * kPi * (1.0 + ab * a.h)) : 0.0;
@@ -554,7 +670,8 @@ __global__ void __launch_bounds__(256)
 k_materialize(long long nc, int ns, double h, const double* __restrict__ map, S* __restrict__ I,
               const double* __restrict__ uhat, const double* __restrict__ dirD,
               const double* __restrict__ w, const double* __restrict__ W16,
-              double* __restrict__ Rout, double* __restrict__ Gout) {
+              double* __restrict__ Rout, double* __restrict__ Gout,
+              const double* __restrict__ nu0, int n3) {
   long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= nc) return;
   if (!MOVING) {
@@ -566,7 +683,9 @@ k_materialize(long long nc, int ns, double h, const double* __restrict__ map, S*
     return;
   }
   const double Q = map[c], ab = map[nc + c];
-  const bool use = map[2 * nc + c] != 0.0;
+  const double code = map[2 * nc + c];  // 1: apply, 0: keep, 2: zero
+  const bool use = code == 1.0, zero = code == 2.0;
+  const double n0c = nu0 ? nu0[c / n3] : 1.0;
   const double u0 = uhat[c], u1 = uhat[nc + c], u2 = uhat[2 * nc + c], u3 = uhat[3 * nc + c];
   double R[10];
   for (int m = 0; m < 10; ++m) R[m] = 0.0;
@@ -578,10 +697,13 @@ k_materialize(long long nc, int ns, double h, const double* __restrict__ map, S*
     if (use) {
       double nb = u0 - (u1 * dirD[s] + u2 * dirD[ns + s] + u3 * dirD[2 * ns + s]);
       double nb2 = nb * nb, nb4 = nb2 * nb2;
-      double den = 1.0 + nb * ab * h;
-      double cs = 1.0 / den, ds = nb * h / (4.0 * kPi * den);
+      double den = n0c + nb * ab * h;
+      double cs = n0c / den, ds = nb * h / (4.0 * kPi * den);
       Io = (cs * It * nb4 + ds * Q) / nb4;
       *q = (S)Io;
+    } else if (zero) {
+      Io = 0.0;
+      *q = (S)0;
     }
     const double Iq = (double)(S)Io;
     if (Rout)
@@ -612,16 +734,22 @@ hipError_t launch_tiled(rt_ctx* c, StageArgs a, const StagePtrs& p, bool stage2,
   a.ntiles = a.tiles_x * a.tiles_y * a.tiles_z;
   a.tiles_per_xcd = (a.ntiles + 7) / 8;
   dim3 grid(8 * a.tiles_per_xcd), block(TX * TY);
-  if (c->moving) {
+  if (c->curved) {
+    // curved geometry always runs the moving-fluid form (direction-dependent map)
     if (stage2)
-      hipLaunchKernelGGL((k_stage<S, F, TY, TZ, true, true, LIM>), grid, block, 0, st, a, p);
+      hipLaunchKernelGGL((k_stage<S, F, TY, TZ, true, true, LIM, true>), grid, block, 0, st, a, p);
     else
-      hipLaunchKernelGGL((k_stage<S, F, TY, TZ, false, true, LIM>), grid, block, 0, st, a, p);
+      hipLaunchKernelGGL((k_stage<S, F, TY, TZ, false, true, LIM, true>), grid, block, 0, st, a, p);
+  } else if (c->moving) {
+    if (stage2)
+      hipLaunchKernelGGL((k_stage<S, F, TY, TZ, true, true, LIM, false>), grid, block, 0, st, a, p);
+    else
+      hipLaunchKernelGGL((k_stage<S, F, TY, TZ, false, true, LIM, false>), grid, block, 0, st, a, p);
   } else {
     if (stage2)
-      hipLaunchKernelGGL((k_stage<S, F, TY, TZ, true, false, LIM>), grid, block, 0, st, a, p);
+      hipLaunchKernelGGL((k_stage<S, F, TY, TZ, true, false, LIM, false>), grid, block, 0, st, a, p);
     else
-      hipLaunchKernelGGL((k_stage<S, F, TY, TZ, false, false, LIM>), grid, block, 0, st, a, p);
+      hipLaunchKernelGGL((k_stage<S, F, TY, TZ, false, false, LIM, false>), grid, block, 0, st, a, p);
   }
   return hipGetLastError();
 }
@@ -643,17 +771,17 @@ hipError_t launch_materialize(rt_ctx* c, void* I, const double* map, double h, d
   if (c->fp32) {
     if (c->moving)
       hipLaunchKernelGGL((k_materialize<float, true>), grid, block, 0, st, c->nc, c->ns, h, map,
-                         (float*)I, c->d_uhat, c->d_dir, c->d_w, c->d_W16, R, G);
+                         (float*)I, c->d_uhat, c->d_dir, c->d_w, c->d_W16, R, G, c->d_nu0, c->n[2]);
     else
       hipLaunchKernelGGL((k_materialize<float, false>), grid, block, 0, st, c->nc, c->ns, h, map,
-                         (float*)I, c->d_uhat, c->d_dir, c->d_w, c->d_W16, R, G);
+                         (float*)I, c->d_uhat, c->d_dir, c->d_w, c->d_W16, R, G, c->d_nu0, c->n[2]);
   } else {
     if (c->moving)
       hipLaunchKernelGGL((k_materialize<double, true>), grid, block, 0, st, c->nc, c->ns, h, map,
-                         (double*)I, c->d_uhat, c->d_dir, c->d_w, c->d_W16, R, G);
+                         (double*)I, c->d_uhat, c->d_dir, c->d_w, c->d_W16, R, G, c->d_nu0, c->n[2]);
     else
       hipLaunchKernelGGL((k_materialize<double, false>), grid, block, 0, st, c->nc, c->ns, h, map,
-                         (double*)I, c->d_uhat, c->d_dir, c->d_w, c->d_W16, R, G);
+                         (double*)I, c->d_uhat, c->d_dir, c->d_w, c->d_W16, R, G, c->d_nu0, c->n[2]);
   }
   return hipGetLastError();
 }

@@ -23,6 +23,10 @@ struct StageArgs {
   double W0;        // sum of the quadrature weights
   double Wsum[10];  // sum_s w_s n^a n^b (moments of a unit isotropic field)
   int tiles_x, tiles_y, tiles_z, ntiles, tiles_per_xcd;
+  // curved (Kerr-Schild) geometry
+  int curved;       // 0: flat Cartesian, 1: per-(r, theta) geometry tables
+  int zin_stride;   // bytes per direction of the boundary incoming flags
+  int pole_rows;    // theta rows next to each axis whose intensity is zeroed
 };
 
 struct StagePtrs {
@@ -48,11 +52,24 @@ struct StagePtrs {
   double* Rout;         // stage 2 at rest: moments of the new intensity (nullable)
   double* Gout;         // stage 2 at rest: 4-force (nullable)
   unsigned long long* fail;
+  // curved geometry (NULL when flat): face records {gP, gN, gA, x} in the
+  // transport type, [ns][faces][4] for faces normal to x1, theta and phi
+  // (the phi records carry the centre factor x), boundary incoming flags,
+  // the angular flux divergence of Iflux already scaled to the update
+  // (transport type, [ns][nc]) and n^0 = 1/lapse per (r, theta)
+  const void* rec_r_v;
+  const void* rec_t_v;
+  const void* rec_p_v;
+  const unsigned char* zin;
+  const void* angD_v;
+  const double* nu0;
 };
 
 hipError_t launch_stage(rt_ctx* c, const StageArgs& a, const StagePtrs& p, bool stage2,
                         hipStream_t st);
 hipError_t launch_materialize(rt_ctx* c, void* I, const double* map, double h, double* R,
                               double* G, hipStream_t st);
+// angular flux divergence of I (curved geometry) into c->d_angD
+hipError_t launch_angular(rt_ctx* c, const void* I, hipStream_t st);
 
 }  // namespace rt

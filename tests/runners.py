@@ -13,9 +13,16 @@ F64 = torch.float64
 
 def gpu_context(wl, precision="fp64", limiter="mc", cfl=0.4):
     import paper_2508_15532_amd as P
-    ctx = P.RTContext(wl["n"], wl["xlo"], wl["xhi"], wl["generation"], weights=wl["weights"],
-                      precision=precision, bc=wl["bc"], bc_hi=wl.get("bc_hi"), limiter=limiter)
-    ctx.set_metric("flat", cfl=cfl)
+    if wl.get("metric") == "kerr_schild":
+        ctx = P.RTContext(wl["n"], wl["xlo"], wl["xhi"], wl["generation"], weights=wl["weights"],
+                          precision=precision, bc=wl["bc"], bc_hi=wl.get("bc_hi"), limiter=limiter,
+                          coords="logr_theta_phi", pole_zero_rows=wl["pole_rows"],
+                          n0_cut=wl["n0_cut"])
+        ctx.set_metric("kerr_schild", M=wl["M"], a=wl["a"], cfl=wl.get("cfl", cfl))
+    else:
+        ctx = P.RTContext(wl["n"], wl["xlo"], wl["xhi"], wl["generation"], weights=wl["weights"],
+                          precision=precision, bc=wl["bc"], bc_hi=wl.get("bc_hi"), limiter=limiter)
+        ctx.set_metric("flat", cfl=cfl)
     dev = torch.device("cuda", 0)
 
     def t(x):
@@ -57,10 +64,17 @@ def gpu_run(wl, steps, precision="fp64", I0=None, limiter="mc", want_G=False):
     return out
 
 
+def oracle_problem(wl, limiter=0):
+    from oracle.setup import build_flat, build_ks
+    if wl.get("metric") == "kerr_schild":
+        pb, I, T, _ = build_ks(wl, limiter=limiter)
+        return pb, I, T
+    return build_flat(wl, limiter=limiter)
+
+
 def oracle_run(wl, steps, I0=None, limiter=0, want_G=False):
     from oracle import step as st
-    from oracle.setup import build_flat
-    pb, I, T = build_flat(wl, limiter=limiter)
+    pb, I, T = oracle_problem(wl, limiter)
     if I0 is not None:
         I = torch.as_tensor(I0, dtype=F64).reshape(I.shape).clone()
     G = None

@@ -70,8 +70,11 @@ def _desc(N, **kw):
     (dict(precision=7), b"precision"),
     (dict(limiter=3), b"limiter"),
     (dict(bc_lo=(0, 0, 0), bc_hi=(1, 0, 0)), b"periodic"),
-    (dict(coords=5), b"coordinates"),
+    (dict(coords=5), b"coords"),
     (dict(weights=4), b"weights"),
+    (dict(coords=1, pole_zero_rows=3), b"pole_zero_rows"),
+    (dict(coords=0, pole_zero_rows=1), b"pole_zero_rows"),
+    (dict(n0_cut=-1.0), b"n0_cut"),
 ])
 def test_bad_descriptors_are_rejected(kw, msg):
     N, lib = _lib()

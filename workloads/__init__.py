@@ -116,8 +116,10 @@ def _ks_equatorial_block(r, th, a):
     return -(1.0 - z), -z * a * s2, s2 * (Sig + a * a * (1.0 + z) * s2)
 
 
-def torus_ks(n=(256, 128, 64), a=0.9, generation=2, sigma_ln=None, scattering=False, seed=None):
-    """Synthetic torus in Kerr-Schild coordinates (x1 = ln r, theta, phi), r in [1.5, 50]:
+def torus_ks(n=(256, 128, 64), a=0.9, generation=2, sigma_ln=None, scattering=False, seed=None,
+             r_in=1.5, r_out=50.0):
+    """Synthetic torus in Kerr-Schild coordinates (x1 = ln r, theta, phi), r in [r_in, r_out]
+    (default [1.5, 50]):
     rho = exp(-(r-12)^2/(2*3^2) - (theta-pi/2)^2/(2*0.3^2)) (times a lognormal field
     when sigma_ln is given); circular Keplerian flow u = u^t (1, 0, 0, Omega),
     Omega = 1/(r^1.5 + a), where r >= r_isco(a) and the orbit is timelike, else
@@ -126,8 +128,8 @@ def torus_ks(n=(256, 128, 64), a=0.9, generation=2, sigma_ln=None, scattering=Fa
     outflow; phi periodic; rows next to the poles zeroed."""
     rng = rng_for(5 if sigma_ln else 2, seed)
     shape = tuple(int(v) for v in n)
-    xlo = (math.log(1.5), 0.0, 0.0)
-    xhi = (math.log(50.0), math.pi, 2.0 * math.pi)
+    xlo = (math.log(r_in), 0.0, 0.0)
+    xhi = (math.log(r_out), math.pi, 2.0 * math.pi)
     x1 = xlo[0] + (np.arange(shape[0]) + 0.5) * (xhi[0] - xlo[0]) / shape[0]
     th = xlo[1] + (np.arange(shape[1]) + 0.5) * (xhi[1] - xlo[1]) / shape[1]
     r = np.exp(x1)[:, None, None] * np.ones(shape)
