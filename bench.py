@@ -23,7 +23,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X published HBM3E bandwidth
-KERNEL_SRC = os.path.join(ROOT, "paper_2508_15532_amd", "csrc", "kernels.hip")
+CSRC = os.path.join(ROOT, "paper_2508_15532_amd", "csrc")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 
 
@@ -51,22 +51,38 @@ def step_algorithmic_bytes(elem, ns, nc):
 
 def make_inputs(wl, ctx, torch):
     dev = torch.device("cuda", 0)
-    rho = torch.as_tensor(wl["rho"], dtype=torch.float64).reshape(-1).to(dev)
-    T = torch.as_tensor(wl["T"], dtype=torch.float64).reshape(-1).to(dev)
-    ctx.set_opacities(wl["model"], rho, gamma=wl["gamma"], C_a=wl["C_a"], C_s=wl["C_s"])
-    I = (T ** 4 / (4 * math.pi)).reshape(1, -1).expand(ctx.ns, -1).to(ctx.intensity_dtype).contiguous()
+
+    def t(x):
+        return None if x is None else torch.as_tensor(x, dtype=torch.float64).reshape(-1).to(dev)
+    rho, T, u = t(wl["rho"]), t(wl["T"]), t(wl.get("u"))
+    ctx.set_opacities(wl["model"], rho, u=u, gamma=wl["gamma"], C_a=wl["C_a"], C_s=wl["C_s"])
+    if wl.get("metric") == "kerr_schild":
+        I0 = torch.as_tensor(wl["I0_iso"], dtype=torch.float64).reshape(-1).to(dev)
+    else:
+        I0 = T ** 4 / (4 * math.pi)
+    I = I0.reshape(1, -1).expand(ctx.ns, -1).to(ctx.intensity_dtype).contiguous()
     R = torch.empty((10, ctx.nc), dtype=torch.float64, device=dev)
-    return rho, I, T, R
+    return (rho, u), I, T, R
+
+
+def make_context(wl, precision, P):
+    if wl.get("metric") == "kerr_schild":
+        ctx = P.RTContext(wl["n"], wl["xlo"], wl["xhi"], wl["generation"], weights=wl["weights"],
+                          precision=precision, bc=wl["bc"], bc_hi=wl["bc_hi"],
+                          coords="logr_theta_phi", pole_zero_rows=wl["pole_rows"], n0_cut=wl["n0_cut"])
+        dt = ctx.set_metric("kerr_schild", M=wl["M"], a=wl["a"], cfl=wl["cfl"])
+        return ctx, dt
+    ctx = P.RTContext(wl["n"], wl["xlo"], wl["xhi"], wl["generation"], weights=wl["weights"],
+                      precision=precision, bc=wl["bc"])
+    ctx.set_metric("flat", cfl=0.4)
+    return ctx, wl["dt"]
 
 
 def run_form(wl, precision, steps, warmup, torch, P, per_call=False):
     """Time `steps` steps of rt_step (moments of every step written to R);
     either one call advancing all steps, or one call per step."""
-    ctx = P.RTContext(wl["n"], wl["xlo"], wl["xhi"], wl["generation"], weights=wl["weights"],
-                      precision=precision, bc=wl["bc"])
-    ctx.set_metric("flat", cfl=0.4)
+    ctx, dt = make_context(wl, precision, P)
     rho, I, T, R = make_inputs(wl, ctx, torch)
-    dt = wl["dt"]
     for _ in range(warmup):
         ctx.step(I, T, dt, 1, R=R)
     torch.cuda.synchronize()
@@ -92,14 +108,23 @@ def run_form(wl, precision, steps, warmup, torch, P, per_call=False):
                 elem=4 if precision == "fp32" else 8)
 
 
+def sources_sha256():
+    """Hash of every kernel and host source of the library (sorted by name)."""
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(CSRC)):
+        if name.endswith((".hip", ".cpp", ".hpp")):
+            h.update(name.encode())
+            h.update(open(os.path.join(CSRC, name), "rb").read())
+    return h.hexdigest()
+
+
 def traffic_for(kernel, elem):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
-    summary, if it was taken on the current kernel source; else None."""
+    summary, if it was taken on the current sources; else None."""
     try:
         with open(TRAFFIC_FILE) as f:
             rec = json.load(f)
-        src = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
-        if rec.get("kernels_sha256") != src:
+        if rec.get("sources_sha256") != sources_sha256():
             return None
         return rec["per_launch_bytes"].get(f"{kernel}_{'fp32' if elem == 4 else 'fp64'}")
     except (OSError, KeyError, ValueError):
@@ -136,7 +161,21 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--forms", default="fp32,fp64")
     ap.add_argument("--no-per-call", action="store_true")
+    ap.add_argument("--no-torus", action="store_true",
+                    help="skip the Kerr-Schild torus line (256x128x64 x 162, FP32)")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain 1 GiB device-to-device copy 5 times (the "
+                         "reference kernel for scaling HBM byte counters) and exit")
     args = ap.parse_args()
+    if args.calibrate_copy:
+        import torch
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": src.numel() * 4, "copy_bytes_written": dst.numel() * 4}))
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU "
               "decomposition is designed but not built", file=sys.stderr)
@@ -209,6 +248,19 @@ def main():
         out["ms_per_step_fp32_one_call_per_step"] = 1e3 * per_call["wall"] / args.steps
     if "fp32" in res and "fp64" in res:
         out["speedup_fp32_over_fp64"] = out["value_fp32"] / out["value_fp64"]
+    if not args.no_torus:
+        # curved geometry: the a = 0.9 Kerr-Schild torus, FP32 transport form
+        print("bench: torus_ks fp32 256x128x64 x 162", file=sys.stderr, flush=True)
+        tw = W.torus_ks()
+        tr = run_form(tw, "fp32", args.steps, args.warmup, torch, P)
+        out["torus_ks"] = {
+            "workload": "Kerr-Schild a=0.9 torus, (ln r, theta, phi) 256x128x64 x 162 directions, "
+                        "Keplerian flow, Method 2, FP32 transport",
+            "value": tr["ns"] * tr["nc"] * args.steps / tr["wall"],
+            "unit": "cell-direction updates/s",
+            "ms_per_step": 1e3 * tr["wall"] / args.steps,
+            "kernels_ms_per_step": {k: v[1] / args.steps for k, v in tr["ktimes"].items() if v[0]},
+            "finite": tr["finite"]}
     if not args.no_cpu_baseline:
         print("bench: CPU oracle baseline", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(torch)

@@ -43,7 +43,7 @@ def build_flat(wl, grid=None, limiter=tr.LIM_MC):
     return pb, I0, T0
 
 
-def build_ks(wl, grid=None, limiter=tr.LIM_MC, fd_h=1e-4):
+def build_ks(wl, grid=None, limiter=tr.LIM_MC, fd_h=1e-3):
     """Problem on the Kerr-Schild (ln r, theta, phi) mesh; returns (pb, I0, T0, dt_max)."""
     from .kerr import KerrSchildLogR
     grid = grid or GeodesicGrid(wl["generation"], wl["weights"])

@@ -122,7 +122,7 @@ rt_status upload(T** dst, const std::vector<T>& v) {
 rt_status set_kerr_schild(rt_ctx* c, double M, double a, double cfl) {
   KsTables T;
   try {
-    T = build_ks_tables(c->grid, c->desc.n, c->desc.xlo, c->desc.xhi, a, M, c->desc.n0_cut, cfl, 1e-4);
+    T = build_ks_tables(c->grid, c->desc.n, c->desc.xlo, c->desc.xhi, a, M, c->desc.n0_cut, cfl, 1e-3);
   } catch (const std::bad_alloc&) {
     return fail(RT_E_NOMEM, "rt_set_metric: host allocation failed");
   } catch (const std::exception& e) {

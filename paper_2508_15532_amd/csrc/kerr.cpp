@@ -20,7 +20,8 @@
 // affine parameter with dx/dlambda = n^mu (the geodesic equation written in
 // the tetrad basis).  The flux through a Voronoi edge of the geodesic grid
 // (Sec. 3.5, donor-cell states) is n_0(m_e) (r(m_e) . u_e) dlambda_e I_upwind.
-// Derivatives are central differences of the analytic metric and tetrad.
+// Derivatives are fourth-order central differences of the analytic metric and
+// tetrad.
 #include "kerr.hpp"
 
 #include <cmath>
@@ -136,13 +137,15 @@ void rotation_coefficients(double x1, double th, double a, double M, double h, d
   inverse4(P.g, gi);
   double dg[4][4][4] = {};  // dg[mu][n][l] = d_mu g_(n l)
   double de[4][4][4] = {};  // de[mu][b][d] = d_mu e^b_d
+  // fourth-order central differences, weights (1, -8, 8, -1) / 12h at -2h .. 2h
   for (int mu = 1; mu <= 2; ++mu) {
     const double d1 = mu == 1 ? h : 0.0, d2 = mu == 2 ? h : 0.0;
-    const Point p = at(x1 + d1, th + d2, a, M), m = at(x1 - d1, th - d2, a, M);
+    const Point p2 = at(x1 + 2 * d1, th + 2 * d2, a, M), p1 = at(x1 + d1, th + d2, a, M);
+    const Point m1 = at(x1 - d1, th - d2, a, M), m2 = at(x1 - 2 * d1, th - 2 * d2, a, M);
     for (int i = 0; i < 4; ++i)
       for (int j = 0; j < 4; ++j) {
-        dg[mu][i][j] = (p.g[i][j] - m.g[i][j]) / (2.0 * h);
-        de[mu][i][j] = (p.e[i][j] - m.e[i][j]) / (2.0 * h);
+        dg[mu][i][j] = (8.0 * (p1.g[i][j] - m1.g[i][j]) - (p2.g[i][j] - m2.g[i][j])) / (12.0 * h);
+        de[mu][i][j] = (8.0 * (p1.e[i][j] - m1.e[i][j]) - (p2.e[i][j] - m2.e[i][j])) / (12.0 * h);
       }
   }
   // Gamma^b_(mu l) = 1/2 g^(b n) (d_mu g_(n l) + d_l g_(n mu) - d_n g_(mu l))
@@ -189,6 +192,9 @@ KsTables build_ks_tables(const GeodesicGrid& G, const int n[3], const double xlo
   T.ns = ns;
   T.ne = ne;
   const double dx[3] = {(xhi[0] - xlo[0]) / N1, (xhi[1] - xlo[1]) / N2, (xhi[2] - xlo[2]) / N3};
+  // the difference stencil of the rotation coefficients must stay off the axis
+  if (!(xlo[1] + 0.5 * dx[1] - 2.0 * fd_h > 0.0) || !(xlo[1] + (N2 - 0.5) * dx[1] + 2.0 * fd_h < M_PI))
+    throw std::invalid_argument("theta cell centres must lie more than 2 fd_h from the axis");
   auto x1c = [&](int i) { return xlo[0] + (i + 0.5) * dx[0]; };
   auto thc = [&](int j) { return xlo[1] + (j + 0.5) * dx[1]; };
   auto x1f = [&](int i) { return xlo[0] + i * dx[0]; };

@@ -38,8 +38,8 @@ struct KsTables {
 };
 
 // Builds the tables for spin a and mass M on the mesh n, [xlo, xhi] with the
-// given geodesic grid.  Rotation coefficients come from central differences
-// with step fd_h of the analytic metric and tetrad.  Throws std::invalid_argument
+// given geodesic grid.  Rotation coefficients come from fourth-order central
+// differences with step fd_h of the analytic metric and tetrad.  Throws std::invalid_argument
 // when the mesh reaches r <= 0 or theta outside [0, pi].
 KsTables build_ks_tables(const GeodesicGrid& g, const int n[3], const double xlo[3],
                          const double xhi[3], double a, double M, double n0_cut, double cfl,

@@ -714,3 +714,29 @@ def test_uniform_isotropic_field_balance_converges_with_angular_resolution():
         assert dsp[:, 3:-3, 3:-3].abs().max() > 0.5
         res.append(float(tot.pow(2).mean().sqrt()))
     assert res[0] > 2.0 * res[1] > 4.0 * res[2] and res[2] < 3e-3
+
+
+def test_coordinate_moments_null_trace_and_observer_energy():
+    """R^(mu nu) = e^mu_a e^nu_b R-hat^(ab): the trace g_(mu nu) R^(mu nu)
+    vanishes because every photon direction is null, and the normal observer
+    (e_0) measures R-hat^00 as its energy density, N_mu N_nu R^(mu nu) =
+    R-hat^00 with N_mu = e_(0) lowered (Eq. R, Sec. 2.1.1)."""
+    from oracle.kerr import coordinate_moments, ks_metric, tetrad
+    G = GeodesicGrid(2)
+    x1 = np.log(np.array([1.7, 4.0, 20.0]))[:, None] * np.ones((3, 2))
+    th = np.array([0.3, 2.2])[None, :] * np.ones((3, 2))
+    g = ks_metric(x1, th, 0.9)
+    e = tetrad(g)
+    I = torch.tensor(W.random_intensity(G.ns, (3, 2, 2), 5))
+    Rh = st.moments(I, G.n, G.w)
+    Rc = coordinate_moments(Rh, e)
+    full = torch.zeros((4, 4) + tuple(Rc.shape[1:]), dtype=F64)
+    for k, (p, q) in enumerate(st.SYM10):
+        full[p, q] = Rc[k]
+        full[q, p] = Rc[k]
+    gt = torch.tensor(g)
+    trace = torch.einsum("ijmn,mnijk->ijk", gt, full)
+    assert trace.abs().max() < 1e-13 * Rh[0].abs().max()
+    Nlow = torch.einsum("ijmn,ijn->ijm", gt, torch.tensor(e[..., :, 0]))
+    E = torch.einsum("ijm,ijn,mnijk->ijk", Nlow, Nlow, full)
+    assert (E - Rh[0]).abs().max() < 1e-12 * Rh[0].abs().max()
