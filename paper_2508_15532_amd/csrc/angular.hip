@@ -11,10 +11,10 @@
 // where |n_0| is below the cut; that factor is applied here, so the stage
 // kernel adds h D' to the spatial update.
 //
-// One workgroup owns a run of up to `cw` cells along phi at one (r, theta)
+// One workgroup owns a run of up to CW cells along phi at one (r, theta)
 // position and holds all their directions in LDS; the geometry of the run is
-// shared (it does not depend on phi), so the edge coefficients are read once
-// per workgroup.
+// shared (it does not depend on phi), so the coefficients are read once per
+// workgroup.
 #include <hip/hip_runtime.h>
 
 #include "ctx.hpp"
@@ -23,61 +23,67 @@
 namespace rt {
 namespace {
 
-template <typename S>
+// D'_s(c) = A_s I_s(c) + sum_k A_(ns+k) I_(o_k)(c) for the incidences k of s,
+// with the per-(r, theta) coefficients A (scaled to the update on the host).
+// CW cells along phi per workgroup; with CW = 64 a wave owns one direction
+// at a time, so the coefficient and incidence reads are wave-uniform.
+template <typename S, int CW>
 __global__ void __launch_bounds__(256)
-k_angular(long long nc, int n3, int ns, int cw, const S* __restrict__ I, S* __restrict__ D,
-          const S* __restrict__ ve, int ne, const S* __restrict__ recp, long long nrt,
-          const S* __restrict__ dV, const int* __restrict__ inc, const double* __restrict__ w) {
+k_angular(long long nc, int n3, int ns, int ninc, const S* __restrict__ I, S* __restrict__ D,
+          const S* __restrict__ coef, const int* __restrict__ inc) {
   extern __shared__ unsigned char smem_raw[];
-  S* col = reinterpret_cast<S*>(smem_raw);  // [ns][cw]
-  const int chunks = (n3 + cw - 1) / cw;
+  S* col = reinterpret_cast<S*>(smem_raw);  // [ns][CW]
+  const int chunks = (n3 + CW - 1) / CW;
   const long long row = blockIdx.x / chunks;  // (i1, i2) position
-  const int x0 = (int)(blockIdx.x % chunks) * cw;
+  const int x0 = (int)(blockIdx.x % chunks) * CW;
   const long long cbase = row * n3 + x0;
   const int t = threadIdx.x;
-  const int ncol = min(cw, n3 - x0);
-  for (int k = t; k < ns * cw; k += 256) {
-    const int s = k / cw, l = k % cw;
+  const int ncol = min(CW, n3 - x0);
+  for (int k = t; k < ns * CW; k += 256) {
+    const int s = k / CW, l = k % CW;
     col[k] = l < ncol ? I[(long long)s * nc + cbase + l] : S(0);
   }
   __syncthreads();
-  const int l = t % cw, grp = t / cw, ngrp = 256 / cw;
-  if (l >= ncol) return;  // no barrier follows
-  const S* v = ve + row * ne * 2;
+  const int l = t % CW;
+  constexpr int NGRP = 256 / CW;
+  int grp = t / CW;
+  if (CW == 64) grp = __builtin_amdgcn_readfirstlane(grp);
+  const S* A = coef + row * (long long)(ns + ninc);
   const int* off = inc;
-  const int* ent = inc + ns + 1;
-  const S dv = dV[row];
-  for (int s = grp; s < ns; s += ngrp) {
-    const S Is = col[s * cw + l];
-    S acc = S(0);
-    for (int k = off[s]; k < off[s + 1]; ++k) {
-      const int e = ent[3 * k], o = ent[3 * k + 1], side = ent[3 * k + 2];
-      const S vP = v[2 * e], vN = v[2 * e + 1];
-      const S It = col[o * cw + l];
-      acc += side > 0 ? vP * Is + vN * It : -(vN * Is + vP * It);
-    }
-    const S x = recp[((long long)s * nrt + row) * 4 + 3];
-    D[(long long)s * nc + cbase + l] = acc * (x * dv / (S)w[s]);
+  const int* other = inc + ns + 1;
+  for (int s = grp; s < ns; s += NGRP) {
+    S acc = A[s] * col[s * CW + l];
+    const int k1 = off[s + 1];
+    for (int k = off[s]; k < k1; ++k) acc += A[ns + k] * col[other[k] * CW + l];
+    if (l < ncol) D[(long long)s * nc + cbase + l] = acc;
   }
+}
+
+template <typename S>
+hipError_t launch_cw(rt_ctx* c, const void* I, hipStream_t st) {
+  const long long nrt = (long long)c->n[0] * c->n[1];
+  const int cw = c->ks_cw;
+  const dim3 grid((unsigned)(nrt * ((c->n[2] + cw - 1) / cw))), block(256);
+  const size_t lds = (size_t)c->ns * cw * sizeof(S);
+  const S* in = (const S*)I;
+  S* out = (S*)c->d_angD;
+  const S* A = (const S*)c->d_acoef;
+  switch (cw) {
+    case 64: hipLaunchKernelGGL((k_angular<S, 64>), grid, block, lds, st, c->nc, c->n[2], c->ns, c->ks_ninc, in, out, A, c->d_inc); break;
+    case 32: hipLaunchKernelGGL((k_angular<S, 32>), grid, block, lds, st, c->nc, c->n[2], c->ns, c->ks_ninc, in, out, A, c->d_inc); break;
+    case 16: hipLaunchKernelGGL((k_angular<S, 16>), grid, block, lds, st, c->nc, c->n[2], c->ns, c->ks_ninc, in, out, A, c->d_inc); break;
+    case 8: hipLaunchKernelGGL((k_angular<S, 8>), grid, block, lds, st, c->nc, c->n[2], c->ns, c->ks_ninc, in, out, A, c->d_inc); break;
+    case 4: hipLaunchKernelGGL((k_angular<S, 4>), grid, block, lds, st, c->nc, c->n[2], c->ns, c->ks_ninc, in, out, A, c->d_inc); break;
+    case 2: hipLaunchKernelGGL((k_angular<S, 2>), grid, block, lds, st, c->nc, c->n[2], c->ns, c->ks_ninc, in, out, A, c->d_inc); break;
+    default: hipLaunchKernelGGL((k_angular<S, 1>), grid, block, lds, st, c->nc, c->n[2], c->ns, c->ks_ninc, in, out, A, c->d_inc); break;
+  }
+  return hipGetLastError();
 }
 
 }  // namespace
 
 hipError_t launch_angular(rt_ctx* c, const void* I, hipStream_t st) {
-  const long long nrt = (long long)c->n[0] * c->n[1];
-  const int cw = c->ks_cw;
-  const long long blocks = nrt * ((c->n[2] + cw - 1) / cw);
-  const size_t lds = (size_t)c->ns * cw * c->elem;
-  if (c->fp32)
-    hipLaunchKernelGGL(k_angular<float>, dim3((unsigned)blocks), dim3(256), lds, st, c->nc, c->n[2],
-                       c->ns, cw, (const float*)I, (float*)c->d_angD, (const float*)c->d_ve, c->ks_ne,
-                       (const float*)c->d_rec_p, nrt, (const float*)c->d_dV, c->d_inc, c->d_w);
-  else
-    hipLaunchKernelGGL(k_angular<double>, dim3((unsigned)blocks), dim3(256), lds, st, c->nc, c->n[2],
-                       c->ns, cw, (const double*)I, (double*)c->d_angD, (const double*)c->d_ve,
-                       c->ks_ne, (const double*)c->d_rec_p, nrt, (const double*)c->d_dV, c->d_inc,
-                       c->d_w);
-  return hipGetLastError();
+  return c->fp32 ? launch_cw<float>(c, I, st) : launch_cw<double>(c, I, st);
 }
 
 }  // namespace rt

@@ -134,18 +134,14 @@ rt_status set_kerr_schild(rt_ctx* c, double M, double a, double cfl) {
   if ((size_t)c->ns * cw * c->elem > 65536)
     return fail(RT_E_ARG, "rt_set_metric: too many directions for the curved FP64 form");
   c->ks_cw = cw;
-  c->ks_ne = T.ne;
+  c->ks_ninc = T.inc_off[c->ns];
   c->ks_zin_stride = T.zin_stride;
   std::vector<int> inc(T.inc_off.begin(), T.inc_off.end());
-  for (size_t k = 0; k < T.inc_edge.size(); ++k) {
-    inc.push_back(T.inc_edge[k]);
-    inc.push_back(T.inc_other[k]);
-    inc.push_back(T.inc_side[k]);
-  }
+  inc.insert(inc.end(), T.inc_other.begin(), T.inc_other.end());
   rt_status st = RT_OK;
   if ((st = upload_as(c, &c->d_rec_r, T.fr)) || (st = upload_as(c, &c->d_rec_t, T.ft)) ||
-      (st = upload_as(c, &c->d_rec_p, T.fp)) || (st = upload_as(c, &c->d_ve, T.ve)) ||
-      (st = upload_as(c, &c->d_dV, T.dV)) || (st = upload(&c->d_zin, T.zin)) ||
+      (st = upload_as(c, &c->d_rec_p, T.fp)) || (st = upload_as(c, &c->d_acoef, T.acoef)) ||
+      (st = upload(&c->d_zin, T.zin)) ||
       (st = upload(&c->d_nu0, T.nu0)) || (st = upload(&c->d_e, T.e)) ||
       (st = upload(&c->d_einv, T.einv)) || (st = upload(&c->d_inc, inc)) ||
       (st = alloc((char**)&c->d_angD, (size_t)c->ns * c->nc * c->elem)))
@@ -435,8 +431,6 @@ rt_status rt_step(rt_ctx* c, void* I, double* T, double dt, int nsteps, double* 
     p.Tstart = T;
     p.Tcoef = T;
     p.Tout = c->d_Tstar;
-    p.Rout = nullptr;
-    p.Gout = nullptr;
     if (c->curved)
       RT_HIP(timed(c, RT_K_ANGULAR, stream, [&] { return launch_angular(c, I, stream); }));
     RT_HIP(timed(c, RT_K_STAGE1, stream, [&] { return launch_stage(c, a, p, false, stream); }));
@@ -458,8 +452,6 @@ rt_status rt_step(rt_ctx* c, void* I, double* T, double dt, int nsteps, double* 
     p.Tstart = T;
     p.Tcoef = c->d_Tstar;
     p.Tout = T;
-    p.Rout = c->moving ? nullptr : R_out;
-    p.Gout = (c->moving || !last) ? nullptr : G_out;
     if (c->curved)
       RT_HIP(timed(c, RT_K_ANGULAR, stream, [&] { return launch_angular(c, c->d_Itil, stream); }));
     RT_HIP(timed(c, RT_K_STAGE2, stream, [&] { return launch_stage(c, a, p, true, stream); }));
@@ -473,8 +465,10 @@ rt_status rt_step(rt_ctx* c, void* I, double* T, double dt, int nsteps, double* 
     }
   }
   if (mapA) {
+    // at rest the last interaction is still a lazy map: apply it, with the
+    // moments and the 4-force of the last step
     RT_HIP(timed(c, RT_K_MATERIALIZE, stream, [&] {
-      return launch_materialize(c, I, mapA, dt, nullptr, nullptr, stream);
+      return launch_materialize(c, I, mapA, dt, R_out, G_out, stream);
     }));
   }
   if (c->debug & 1) {
@@ -600,8 +594,7 @@ void rt_destroy(rt_ctx* c) {
   release(c->d_rec_t);
   release(c->d_rec_p);
   release(c->d_zin);
-  release(c->d_ve);
-  release(c->d_dV);
+  release(c->d_acoef);
   release(c->d_nu0);
   release(c->d_e);
   release(c->d_einv);

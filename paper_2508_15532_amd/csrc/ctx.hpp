@@ -26,17 +26,16 @@ struct rt_ctx {
   double dt_max = 0;
   // Kerr-Schild tables on the device (curved geometry; NULL when flat)
   bool curved = false;
-  int ks_ne = 0, ks_zin_stride = 0, ks_cw = 64;
+  int ks_ninc = 0, ks_zin_stride = 0, ks_cw = 64;
   void* d_rec_r = nullptr;       // [ns][(N1+1) N2][4] transport type
   void* d_rec_t = nullptr;       // [ns][N1 (N2+1)][4]
   void* d_rec_p = nullptr;       // [ns][N1 N2][4]
   unsigned char* d_zin = nullptr;
-  void* d_ve = nullptr;          // [N1 N2][ne][2] transport type
-  void* d_dV = nullptr;          // [N1 N2] transport type
+  void* d_acoef = nullptr;       // [N1 N2][ns + ninc] angular coefficients, transport type
   double* d_nu0 = nullptr;       // [N1 N2]
   double* d_e = nullptr;         // [N1 N2][16] e^mu_a
   double* d_einv = nullptr;      // [N1 N2][16] e^a_mu
-  int* d_inc = nullptr;          // [ns+1] offsets, then [ninc][3] (edge, other, side)
+  int* d_inc = nullptr;          // [ns+1] incidence offsets, then [ninc] other direction
   void* d_angD = nullptr;        // [ns][nc] angular divergence scratch
 
   // device grid tables

@@ -366,6 +366,30 @@ KsTables build_ks_tables(const GeodesicGrid& G, const int n[3], const double xlo
     T.inc_other[k] = s;
     T.inc_side[k] = -1;
   }
+
+  // ---- angular coefficients: the edge flux F_e = vP I_first + vN I_second
+  // enters direction s with + (s first) or - (s second)
+  const int ninc = T.inc_off[ns];
+  T.acoef.assign(nrt * (ns + ninc), 0.0);
+  for (size_t q = 0; q < nrt; ++q) {
+    double* A = &T.acoef[q * (ns + ninc)];
+    for (int s = 0; s < ns; ++s) {
+      const double x = T.fp[((size_t)s * nrt + q) * 4 + 3];
+      const double scale = x * T.dV[q] / G.w[s];  // 1/(w_s n^0 n_0), 0 below the cut
+      double diag = 0.0;
+      for (int k = T.inc_off[s]; k < T.inc_off[s + 1]; ++k) {
+        const double vP = T.ve[(q * ne + T.inc_edge[k]) * 2], vN = T.ve[(q * ne + T.inc_edge[k]) * 2 + 1];
+        if (T.inc_side[k] > 0) {
+          diag += vP;
+          A[ns + k] = scale * vN;
+        } else {
+          diag -= vN;
+          A[ns + k] = -scale * vP;
+        }
+      }
+      A[s] = scale * diag;
+    }
+  }
   return T;
 }
 

@@ -34,6 +34,10 @@ struct KsTables {
   // inc[inc_off[s] .. inc_off[s+1]) = (edge, other direction, +1 if s is the
   // edge's first vertex else -1)
   std::vector<int> inc_off, inc_edge, inc_other, inc_side;
+  // angular flux divergence as the update needs it, per (r, theta):
+  // D'_s = acoef[s] I_s + sum_k acoef[ns + k] I_(other k), k over the incidences
+  // of s; the factors 1/w_s and 1/(n^0 n_0) (zero below the n_0 cut) are folded in
+  std::vector<double> acoef;  // [n1*n2][ns + ninc]
   double dt_max = 0.0;  // cfl * min over cells and axes of dx^a / max_s |n^a / n^0|
 };
 

@@ -430,8 +430,8 @@ k_stage(StageArgs a, StagePtrs p) {
     nu0k[k] = CURVED ? p.nu0[c / n3] : 1.0;
   }
 
-  // accumulators: at rest sum w n^a n^b I~ (10, E_- is the first); moving E_-, A1, A2
-  constexpr int NACC = MOVING ? 3 : (STAGE2 ? 10 : 1);
+  // accumulators: at rest E_- = sum w I~; moving E_-, A1, A2
+  constexpr int NACC = MOVING ? 3 : 1;
   double acc[TZ][NACC];
 #pragma unroll
   for (int k = 0; k < TZ; ++k)
@@ -596,9 +596,6 @@ k_stage(StageArgs a, StagePtrs p) {
         acc[k][0] += Ib * dOb;
         acc[k][1] += nu0k[k] * Ib * dOb / den;
         acc[k][2] += nb * a.h / (4.0 * kPi * den) * dOb;
-      } else if (STAGE2) {
-#pragma unroll
-        for (int m = 0; m < 10; ++m) acc[k][m] += p.W16[s * 16 + m] * Itd;
       } else {
         acc[k][0] += ws * Itd;
       }
@@ -645,14 +642,6 @@ k_stage(StageArgs a, StagePtrs p) {
       const double be = use ? a.h * so.Q / (4.0 * kPi * (1.0 + ab * a.h)) : 0.0;
       p.mapO[c] = al;
       p.mapO[nc + c] = be;
-      if (STAGE2 && p.Rout) {
-        for (int m = 0; m < 10; ++m) p.Rout[m * nc + c] = al * acc[k][m] + be * a.Wsum[m];
-      }
-      if (STAGE2 && p.Gout) {
-        // 4-force on the fluid: -(R^(0a)(out) - R^(0a)(I~)) / h
-        for (int m = 0; m < 4; ++m)
-          p.Gout[m * nc + c] = -((al - 1.0) * acc[k][m] + be * a.Wsum[m]) / a.h;
-      }
     }
   }
 }
@@ -676,10 +665,33 @@ k_materialize(long long nc, int ns, double h, const double* __restrict__ map, S*
   if (c >= nc) return;
   if (!MOVING) {
     const double al = map[c], be = map[nc + c];
+    if (!Rout && !Gout) {
+      for (int s = 0; s < ns; ++s) {
+        S* q = I + (long long)s * nc + c;
+        *q = (S)(al * (double)*q + be);
+      }
+      return;
+    }
+    // moments of the stored new intensity; 4-force -(R^(0a)(out) - R^(0a)(I~)) / h
+    double R[10];
+    for (int m = 0; m < 10; ++m) R[m] = 0.0;
+    double g[4] = {0.0, 0.0, 0.0, 0.0};
     for (int s = 0; s < ns; ++s) {
       S* q = I + (long long)s * nc + c;
-      *q = (S)(al * (double)*q + be);
+      const double It = (double)*q;
+      const S o = (S)(al * It + be);
+      *q = o;
+      const double Iq = (double)o;
+      const double* Ws = W16 + s * 16;
+#pragma unroll
+      for (int m = 0; m < 10; ++m) R[m] += Ws[m] * Iq;
+#pragma unroll
+      for (int m = 0; m < 4; ++m) g[m] += Ws[m] * (Iq - It);
     }
+    if (Rout)
+      for (int m = 0; m < 10; ++m) Rout[m * nc + c] = R[m];
+    if (Gout)
+      for (int m = 0; m < 4; ++m) Gout[m * nc + c] = -g[m] / h;
     return;
   }
   const double Q = map[c], ab = map[nc + c];

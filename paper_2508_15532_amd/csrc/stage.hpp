@@ -49,8 +49,6 @@ struct StagePtrs {
   const double* dirD;   // [3][ns] directions in double
   const double* w;      // [ns]
   const double* W16;    // [ns][16] moment weights
-  double* Rout;         // stage 2 at rest: moments of the new intensity (nullable)
-  double* Gout;         // stage 2 at rest: 4-force (nullable)
   unsigned long long* fail;
   // curved geometry (NULL when flat): face records {gP, gN, gA, x} in the
   // transport type, [ns][faces][4] for faces normal to x1, theta and phi
