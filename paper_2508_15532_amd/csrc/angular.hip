@@ -39,9 +39,22 @@ k_angular(long long nc, int n3, int ns, int ninc, const S* __restrict__ I, S* __
   const long long cbase = row * n3 + x0;
   const int t = threadIdx.x;
   const int ncol = min(CW, n3 - x0);
-  for (int k = t; k < ns * CW; k += 256) {
-    const int s = k / CW, l = k % CW;
-    col[k] = l < ncol ? I[(long long)s * nc + cbase + l] : S(0);
+  // batches of 16 independent loads per thread keep enough reads in flight
+  constexpr int B = 16;
+  const int total = ns * CW;
+  for (int k0 = t; k0 < total; k0 += B * 256) {
+    S v[B];
+#pragma unroll
+    for (int u = 0; u < B; ++u) {
+      // clamped indices keep every load in bounds, so none needs a branch
+      const int k = min(k0 + u * 256, total - 1);
+      const int s = k / CW, l = k % CW;
+      const S x = I[(long long)s * nc + cbase + min(l, ncol - 1)];
+      v[u] = l < ncol ? x : S(0);
+    }
+#pragma unroll
+    for (int u = 0; u < B; ++u)
+      if (k0 + u * 256 < total) col[k0 + u * 256] = v[u];
   }
   __syncthreads();
   const int l = t % CW;

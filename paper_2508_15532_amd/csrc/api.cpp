@@ -186,7 +186,8 @@ rt_status rt_init_grid(const rt_grid_desc* d, rt_ctx** out) {
   if (d->limiter != RT_LIM_MC && d->limiter != RT_LIM_MINMOD) return fail(RT_E_ARG, "rt_init_grid: bad limiter");
   if (!(d->abar >= 0.0) || !(d->rho_floor >= 0.0)) return fail(RT_E_ARG, "rt_init_grid: abar, rho_floor >= 0");
   long long nc = (long long)d->n[0] * d->n[1] * d->n[2];
-  if (nc > (1ll << 40)) return fail(RT_E_ARG, "rt_init_grid: too many cells");
+  // cell indices are 32-bit inside the stage kernels
+  if (nc >= (1ll << 31)) return fail(RT_E_ARG, "rt_init_grid: at most 2^31 - 1 cells");
 
   rt_ctx* c = nullptr;
   try {
@@ -590,6 +591,7 @@ void rt_destroy(rt_ctx* c) {
   release(c->d_gD);
   release(c->d_gcell);
   release(c->d_count);
+  release(c->d_tile_order);
   release(c->d_rec_r);
   release(c->d_rec_t);
   release(c->d_rec_p);

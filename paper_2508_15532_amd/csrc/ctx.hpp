@@ -68,6 +68,10 @@ struct rt_ctx {
   void* d_gD = nullptr;
   double* d_gcell = nullptr;   // adjoint per-face tau gradients [3][2][nc]
   unsigned long long* d_count = nullptr;  // [0] interaction failures, [1] non-finite
+  // launch order of the stage kernel's tiles (bricks of tiles that run together),
+  // cached per (tiles per axis, tile shape, resident workgroups)
+  unsigned* d_tile_order = nullptr;
+  long long tile_order_key = -1;
   int debug = 0;
   // kernel timing (debug bit 1): events recorded around launches
   struct Timed {

@@ -2,11 +2,8 @@
 // PLI transport of every direction, and the per-cell sums and implicit
 // temperature solve of the interaction, in one pass over the intensities.
 //
-// Work decomposition.  A workgroup owns a tile of 64 (i3) x TY (i2) x TZ (i1)
-// cells and loops over all directions.  Thread (tx, ty) owns the column of TZ
-// cells at (i2 = y0 + ty, i3 = x0 + tx).  For each direction the tile and a
-// two-cell halo (the PLI stencil) are staged in LDS; the i1 faces of a column
-// are computed once per face (column march), the i2 and i3 faces from LDS.
+// Work decomposition: see the kernel below (64 x 4 x TZ cell tiles, a column
+// of TZ cells per thread, all directions looped inside the workgroup).
 //
 // Lazy interaction.  At rest the implicit update of a cell is affine in the
 // transported intensity, I_out = alpha I~ + beta for every direction, with
@@ -19,8 +16,10 @@
 // separate materialisation pass follows each stage.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <type_traits>
+#include <vector>
 
 #include "ctx.hpp"
 #include "stage.hpp"
@@ -172,48 +171,59 @@ __device__ Solve solve_cell(const StageArgs& a, double r, double T0, double aa, 
 // ---------------------------------------------------------------------------
 // the fused stage kernel
 //
-// Per direction s, with two LDS buffers alternating between directions:
-//   1. stage the tile's region (cells plus a two-cell cross halo) of the flux
-//      intensity, with its lazy map applied and zero-incoming ghosts zeroed;
-//   2. compute every face flux of the tile once (face-parallel thread mapping:
-//      faces along i3, i2 and i1 are flattened and dealt round-robin to the
-//      workgroup's threads) into LDS;
-//   3. each thread forms the divergence of its own cells, writes I~ and adds
-//      the cell's interaction sums (FP64).
+// Work decomposition.  A workgroup of 256 threads owns a tile of 64 (i3, x) x
+// 4 (i2, y) x TZ (i1, z) cells and loops over all directions.  Wave ty owns row
+// y0 + ty, lane tx column x0 + tx, and each thread the TZ cells of its column
+// along z.  For each direction:
+//   1. the thread's column with a two-cell halo along z lives in registers
+//      (the z stencil needs no data movement); the TZ planes of the tile with
+//      a two-cell halo in x and y are staged in LDS (lazy map applied,
+//      zero-incoming ghosts zeroed);
+//   2. every thread computes the face fluxes below its cells along x and y
+//      (stencils from LDS) and all TZ + 1 z faces of its column (registers);
+//      the x faces above the tile's last column and the y faces above its last
+//      row are shared out over otherwise idle lanes; x and y fluxes go to LDS;
+//   3. each thread forms the divergence of its cells (upper x and y faces are
+//      the neighbours' lower faces), writes I~ and adds the cell's FP64
+//      interaction sums.
+// LDS buffers alternate between directions, so two barriers per direction
+// suffice; the next direction's intensities are loaded during steps 2-3.
 // After the last direction each thread solves the temperature equation of its
-// cells and writes the cell's lazy interaction map.
+// cells and writes the cell's interaction map.
 // ---------------------------------------------------------------------------
-template <typename S, typename F, int TY, int TZ, bool STAGE2, bool MOVING, int LIM, bool CURVED>
-__global__ void __launch_bounds__(TX* TY)
+template <typename S, typename F, int TZ, bool STAGE2, bool MOVING, int LIM, bool CURVED>
+__global__ void __launch_bounds__(256)
 k_stage(StageArgs a, StagePtrs p) {
-  constexpr int NT = TX * TY;
-  constexpr int RX = TX + 4, RY = TY + 4, RZ = TZ + 4;
-  constexpr int NREG = RX * RY * RZ;
-  constexpr int NJ = (NREG + NT - 1) / NT;
-  // faces of the tile along i3 (x), i2 (y), i1 (z)
-  constexpr int NFX = TZ * TY * (TX + 1), NFY = TZ * (TY + 1) * TX, NFZ = (TZ + 1) * TY * TX;
-  constexpr int JX = (NFX + NT - 1) / NT, JY = (NFY + NT - 1) / NT, JZ = (NFZ + NT - 1) / NT;
-  // every staging slot and every face slot owns an LDS word, so the loops below
-  // run without per-slot branches (slots outside the region / face set write
-  // words nobody reads)
-  constexpr int OFY = JX * NT, OFZ = (JX + JY) * NT;
-  __shared__ F reg[2][NJ * NT];
-  __shared__ F flx[2][(JX + JY + JZ) * NT];
-  // curved geometry: per-direction face records of the tile, {gP, gN, gA, x},
-  // for the x1 faces ((TZ+1) x TY), theta faces (TZ x (TY+1)) and phi rows /
-  // centres (TZ x TY), staged like the intensity region
-  constexpr int NRR = (TZ + 1) * TY, NRT = TZ * (TY + 1), NRP = TZ * TY;
-  constexpr int NREC = NRR + NRT + NRP;
+  constexpr int TY = 4, NT = TX * TY;
+  constexpr int RX = TX + 4, RY = TY + 4;
+  constexpr int NW = TZ + 4;  // column window: planes z0-2 .. z0+TZ+1
+  static_assert(TZ <= TY, "the extra y faces are shared out one plane per wave");
+  // curved geometry: per-direction face records {gP, gN, gA, x} for the x
+  // (phi) rows (k, ty) -- x holds the centre factor --, the y (theta) faces
+  // (k, 0..TY) and the z (r) faces (0..TZ, ty)
+  constexpr int NRX = TZ * TY, NRY = TZ * (TY + 1), NRZ = (TZ + 1) * TY;
+  constexpr int NREC = NRX + NRY + NRZ;
   static_assert(!CURVED || NREC * 4 <= NT, "one record word per thread");
+  __shared__ F pl[2][TZ][RY][RX];         // planes of the tile with x/y halo
+  __shared__ F fxs[2][TZ][TY][TX + 1];    // x faces: lower face of each cell, then the last
+  __shared__ F fys[2][TZ][TY + 1][TX];    // y faces
   __shared__ F grec[CURVED ? 2 : 1][CURVED ? NREC * 4 : 1];
 
-  // ---- tile of this workgroup (XCD-aware: each XCD gets a contiguous range)
+  // ---- tile (XCD-aware order)
   const int b = blockIdx.x;
   const int tile = (b % 8) * a.tiles_per_xcd + b / 8;
   if (tile >= a.ntiles) return;
-  const int bx = tile % a.tiles_x;
-  const int by = (tile / a.tiles_x) % a.tiles_y;
-  const int bz = tile / (a.tiles_x * a.tiles_y);
+  int bx, by, bz;
+  if (p.tile_order) {
+    const unsigned code = p.tile_order[tile];
+    bx = (int)(code & 1023u);
+    by = (int)((code >> 10) & 2047u);
+    bz = (int)(code >> 21);
+  } else {
+    bx = tile % a.tiles_x;
+    by = (tile / a.tiles_x) % a.tiles_y;
+    bz = tile / (a.tiles_x * a.tiles_y);
+  }
   const int x0 = bx * TX, y0 = by * TY, z0 = bz * TZ;
   const int t = threadIdx.x, tx = t % TX, ty = t / TX;
   const int n1 = a.n1, n2 = a.n2, n3 = a.n3;
@@ -221,197 +231,152 @@ k_stage(StageArgs a, StagePtrs p) {
   const S* __restrict__ Iflux = (const S*)p.Iflux_v;
   const S* Ibase = (const S*)p.Ibase_v;  // may alias Iout (same cell, earlier direction)
   S* Iout = (S*)p.Iout_v;
-  const F* __restrict__ dirF = (const F*)p.dirF_v;
   const bool per0 = a.bc_lo[0] == RT_BC_PERIODIC, per1 = a.bc_lo[1] == RT_BC_PERIODIC,
              per2 = a.bc_lo[2] == RT_BC_PERIODIC;
-  auto gcell = [&](int z, int y, int x) -> long long {
-    return ((long long)wrap_clamp(z, n1, per0) * n2 + wrap_clamp(y, n2, per1)) * n3 +
-           wrap_clamp(x, n3, per2);
+  auto gcell = [&](int z, int y, int x) -> int {
+    return (int)(((long long)wrap_clamp(z, n1, per0) * n2 + wrap_clamp(y, n2, per1)) * n3 +
+                 wrap_clamp(x, n3, per2));
   };
-
-  // ---- region elements this thread stages every direction
-  int gidx[NJ];      // global cell (after wrap / clamp); a valid cell for unused slots
-  F mA[NJ], mB[NJ];  // lazy interaction map of the staged cell (identity if none)
-  // zero-incoming sides the slot lies outside of (6 bits per slot, packed)
-  static_assert(NJ * 6 <= 96, "slot flags");
-  unsigned zf[(NJ * 6 + 31) / 32];
-#pragma unroll
-  for (int q = 0; q < (NJ * 6 + 31) / 32; ++q) zf[q] = 0;
-  // curved: offset of the slot's boundary face in the incoming flags (-1: none)
-  int zoff[CURVED ? NJ : 1];
-#pragma unroll
-  for (int j = 0; j < NJ; ++j) {
-    const int k = t + j * NT;
-    int gi = -1;
-    F ma = F(1), mb = F(0);
-    if (CURVED) zoff[j] = -1;
-    if (k < NREG) {
-      const int rx = k % RX, ry = (k / RX) % RY, rz = k / (RX * RY);
-      const bool hz = rz < 2 || rz >= TZ + 2, hy = ry < 2 || ry >= TY + 2, hx = rx < 2 || rx >= TX + 2;
-      if ((int)hz + (int)hy + (int)hx <= 1) {
-        const int gz = z0 - 2 + rz, gy = y0 - 2 + ry, gx = x0 - 2 + rx;
-        unsigned f = 0;
-        if (gz < 0 && a.bc_lo[0] == RT_BC_ZERO_INCOMING) f |= 1u;
-        if (gz >= n1 && a.bc_hi[0] == RT_BC_ZERO_INCOMING) f |= 2u;
-        if (gy < 0 && a.bc_lo[1] == RT_BC_ZERO_INCOMING) f |= 4u;
-        if (gy >= n2 && a.bc_hi[1] == RT_BC_ZERO_INCOMING) f |= 8u;
-        if (gx < 0 && a.bc_lo[2] == RT_BC_ZERO_INCOMING) f |= 16u;
-        if (gx >= n3 && a.bc_hi[2] == RT_BC_ZERO_INCOMING) f |= 32u;
-        if (CURVED) {
-          // flags of the boundary face of the slot's line; slots outside two
-          // sides at once (tile overhang corners) feed no valid cell and keep -1
-          const int b2 = 2 * n2, b1 = 2 * n2 + n1, bp = 2 * n2 + 2 * n1, np = n1 * n2;
-          const bool iz = gz >= 0 && gz < n1, iy = gy >= 0 && gy < n2, ix = gx >= 0 && gx < n3;
-          zoff[j] = ((f & 1u) && iy && ix) ? gy
-                  : ((f & 2u) && iy && ix) ? n2 + gy
-                  : ((f & 4u) && iz && ix) ? b2 + gz
-                  : ((f & 8u) && iz && ix) ? b1 + gz
-                  : ((f & 16u) && iz && iy) ? bp + gz * n2 + gy
-                  : ((f & 32u) && iz && iy) ? bp + np + gz * n2 + gy : -1;
-        } else {
-          zf[(j * 6) / 32] |= f << ((j * 6) % 32);
-          if ((j * 6) % 32 > 26) zf[(j * 6) / 32 + 1] |= f >> (32 - (j * 6) % 32);
-        }
-        gi = (int)gcell(gz, gy, gx);
-        if (p.mapF) {
-          ma = (F)p.mapF[gi];
-          mb = (F)p.mapF[nc + gi];
-        }
-      }
+  // sides of the domain a position lies outside of, where the boundary is
+  // zero-incoming (bits: z lo, z hi, y lo, y hi, x lo, x hi)
+  auto zi_flags = [&](int z, int y, int x) -> unsigned {
+    unsigned f = 0;
+    if (z < 0 && a.bc_lo[0] == RT_BC_ZERO_INCOMING) f |= 1u;
+    if (z >= n1 && a.bc_hi[0] == RT_BC_ZERO_INCOMING) f |= 2u;
+    if (y < 0 && a.bc_lo[1] == RT_BC_ZERO_INCOMING) f |= 4u;
+    if (y >= n2 && a.bc_hi[1] == RT_BC_ZERO_INCOMING) f |= 8u;
+    if (x < 0 && a.bc_lo[2] == RT_BC_ZERO_INCOMING) f |= 16u;
+    if (x >= n3 && a.bc_hi[2] == RT_BC_ZERO_INCOMING) f |= 32u;
+    return f;
+  };
+  // curved: offset of a position's boundary face in the incoming flags (-1:
+  // inside, or outside two sides at once -- such cells feed no valid cell)
+  auto zi_offset = [&](unsigned f, int z, int y, int x) -> int {
+    const int b2 = 2 * n2, b1 = 2 * n2 + n1, bp = 2 * n2 + 2 * n1, np = n1 * n2;
+    const bool iz = z >= 0 && z < n1, iy = y >= 0 && y < n2, ix = x >= 0 && x < n3;
+    return ((f & 1u) && iy && ix) ? y
+         : ((f & 2u) && iy && ix) ? n2 + y
+         : ((f & 4u) && iz && ix) ? b2 + z
+         : ((f & 8u) && iz && ix) ? b1 + z
+         : ((f & 16u) && iz && iy) ? bp + z * n2 + y
+         : ((f & 32u) && iz && iy) ? bp + np + z * n2 + y : -1;
+  };
+  auto map_of = [&](int cell, F& ma, F& mb) {
+    ma = F(1);
+    mb = F(0);
+    if (p.mapF) {
+      ma = (F)p.mapF[cell];
+      mb = (F)p.mapF[nc + cell];
     }
-    gidx[j] = gi >= 0 ? gi : (int)gcell(z0, y0, x0);
-    mA[j] = ma;
-    mB[j] = mb;
-  }
-  bool anyzf = false;
-#pragma unroll
-  for (int q = 0; q < (NJ * 6 + 31) / 32; ++q) anyzf |= zf[q] != 0u;
-  if (CURVED) {
-#pragma unroll
-    for (int j = 0; j < NJ; ++j) anyzf |= zoff[j] >= 0;
-  }
-  auto slot_flags = [&](int j) -> unsigned {
-    const int bit = j * 6, w = bit / 32, o = bit % 32;
-    unsigned v = zf[w] >> o;
-    if (o > 26) v |= zf[w + 1] << (32 - o);
-    return v & 63u;
   };
 
-  // ---- own cells
-  long long own[TZ];
-  bool valid[TZ];
+  // ---- what this thread loads every direction
   const int gx = x0 + tx, gy = y0 + ty;
+  // column window j = 0..NW-1 at z = z0 - 2 + j
+  int wcell[NW];
+  F wA[NW], wB[NW];
+  unsigned long long wflag = 0;  // 6 bits per window slot
+  static_assert(6 * NW <= 64 && 6 * TZ <= 32, "zero-incoming flag packing");
+  int wzoff[CURVED ? NW : 1];
+#pragma unroll
+  for (int j = 0; j < NW; ++j) {
+    const int gz = z0 - 2 + j;
+    wcell[j] = gcell(gz, gy, gx);
+    map_of(wcell[j], wA[j], wB[j]);
+    const unsigned f = zi_flags(gz, gy, gx);
+    if (CURVED) wzoff[j] = zi_offset(f, gz, gy, gx);
+    else wflag |= (unsigned long long)f << (6 * j);
+  }
+  // y halo: row hr = ty of {y0-2, y0-1, y0+TY, y0+TY+1} for the TZ own planes
+  const int hry = ty < 2 ? ty : TY + ty;  // region row
+  const int hgy = y0 - 2 + hry;
+  int ycell[TZ];
+  F yA[TZ], yB[TZ];
+  unsigned yflag = 0;
+  int yzoff[CURVED ? TZ : 1];
 #pragma unroll
   for (int k = 0; k < TZ; ++k) {
-    const int gz = z0 + k;
-    valid[k] = gx < n3 && gy < n2 && gz < n1;
-    own[k] = valid[k] ? ((long long)gz * n2 + gy) * n3 + gx : 0;
+    ycell[k] = gcell(z0 + k, hgy, gx);
+    map_of(ycell[k], yA[k], yB[k]);
+    const unsigned f = zi_flags(z0 + k, hgy, gx);
+    if (CURVED) yzoff[k] = zi_offset(f, z0 + k, hgy, gx);
+    else yflag |= f << (6 * k);
   }
+  // x halo: lanes < 4 TZ of each wave, column hc = lane % 4 of {x0-2, x0-1,
+  // x0+TX, x0+TX+1} on row ty, plane lane / 4
+  const bool xh = tx < 4 * TZ;
+  const int hcol = tx % 4, hk = (tx / 4) % TZ;
+  const int hrx = hcol < 2 ? hcol : TX + hcol;  // region column
+  const int hgx = x0 - 2 + hrx;
+  const int xcell = gcell(z0 + hk, gy, hgx);
+  F xA, xB;
+  map_of(xcell, xA, xB);
+  const unsigned xflag = zi_flags(z0 + hk, gy, hgx);
+  const int xzoff = CURVED ? zi_offset(xflag, z0 + hk, gy, hgx) : -1;
+
+  // ---- own cells (the window's planes 2 .. TZ+1; overhang cells are not stored)
+  bool valid[TZ];
+#pragma unroll
+  for (int k = 0; k < TZ; ++k) valid[k] = gx < n3 && gy < n2 && z0 + k < n1;
+  auto own = [&](int k) -> long long { return wcell[k + 2]; };
 
   // ---- coefficients of the faces this thread computes (direction independent)
-  auto ahat_of = [&](long long c) -> double {
+  auto ahat_of = [&](int c) -> double {
     double aa, as;
     opac(a, p.rho, p.Tcoef, p.ka, p.ks, c, aa, as);
     return (MOVING ? p.uhat[c] : 1.0) * (aa + as);
   };
-  auto vel_of = [&](int axis, int z, int y, int x) -> double { return p.vel[axis * nc + gcell(z, y, x)]; };
-  constexpr int JF = JX + JY + JZ;
-  FaceC<F> fc[JF];
-  F adL[MOVING ? JF : 1], adR[MOVING ? JF : 1];
-  // face slot q -> (axis, tile-relative z, y, x of the cell on the upper side of the face)
-  auto face_of = [&](int q, int& axis, int& fz, int& fy, int& fx) -> bool {
-    int i;
-    if (q < JX) {
-      axis = 2;
-      i = t + q * NT;
-      if (i >= NFX) return false;
-      fx = i % (TX + 1);
-      fy = (i / (TX + 1)) % TY;
-      fz = i / ((TX + 1) * TY);
-    } else if (q < JX + JY) {
-      axis = 1;
-      i = t + (q - JX) * NT;
-      if (i >= NFY) return false;
-      fx = i % TX;
-      fy = (i / TX) % (TY + 1);
-      fz = i / (TX * (TY + 1));
-    } else {
-      axis = 0;
-      i = t + (q - JX - JY) * NT;
-      if (i >= NFZ) return false;
-      fx = i % TX;
-      fy = (i / TX) % TY;
-      fz = i / (TX * TY);
-    }
-    return true;
+  // the face between cells (z, y, x) - d and (z, y, x) along axis `axis`
+  struct Face {
+    F u, v, d;     // E Wu, E Wd, Dc:  P = u + d, Q = v - d
+    F aL, aR;      // advection: (1-E) max(vL, 0), (1-E) min(vR, 0)
   };
-  int fr0[JF];  // region index of the cell on the upper side of each face slot (-1: none)
-  int frec[CURVED ? JF : 1];  // curved: record of each face slot
-#pragma unroll
-  for (int q = 0; q < JF; ++q) {
-    int axis, fz, fy, fx;
-    fc[q] = FaceC<F>{F(0), F(0), F(0), F(0)};
-    if (MOVING) adL[q] = adR[q] = F(0);
-    fr0[q] = ((2 + 0) * RY + 2) * RX + 2;  // any interior word for unused slots
-    if (CURVED) frec[q] = 0;
-    if (!face_of(q, axis, fz, fy, fx)) continue;
-    fr0[q] = ((fz + 2) * RY + fy + 2) * RX + fx + 2;
-    if (CURVED)
-      frec[q] = axis == 0 ? fz * TY + fy : (axis == 1 ? NRR + fz * (TY + 1) + fy : NRR + NRT + fz * TY + fy);
-    const int z = z0 + fz, y = y0 + fy, x = x0 + fx;
+  auto make_face = [&](int axis, int z, int y, int x) -> Face {
     const int dz = axis == 0, dy = axis == 1, dx = axis == 2;
-    const double tau =
-        a.abar * 0.5 * (ahat_of(gcell(z - dz, y - dy, x - dx)) + ahat_of(gcell(z, y, x))) * a.dt;
+    const double tau = a.abar * 0.5 * (ahat_of(gcell(z - dz, y - dy, x - dx)) + ahat_of(gcell(z, y, x))) * a.dt;
     double P, Q, U, V, E;
     face_coefs(tau, P, Q, U, V, E);
-    fc[q] = FaceC<F>{(F)P, (F)Q, (F)(2.0 * U), (F)(2.0 * V)};
+    Face fc;
+    fc.u = (F)(2.0 * U);
+    fc.v = (F)(2.0 * V);
+    fc.d = (F)(P - 2.0 * U);
+    fc.aL = fc.aR = F(0);
     if (MOVING) {
-      // PLI of the coordinate velocity either side of the face
-      const double vm2 = vel_of(axis, z - 2 * dz, y - 2 * dy, x - 2 * dx);
-      const double vm1 = vel_of(axis, z - dz, y - dy, x - dx);
-      const double v0 = vel_of(axis, z, y, x);
-      const double vp1 = vel_of(axis, z + dz, y + dy, x + dx);
+      const double* vel = p.vel + axis * nc;
+      const double vm2 = vel[gcell(z - 2 * dz, y - 2 * dy, x - 2 * dx)];
+      const double vm1 = vel[gcell(z - dz, y - dy, x - dx)];
+      const double v0 = vel[gcell(z, y, x)];
+      const double vp1 = vel[gcell(z + dz, y + dy, x + dx)];
       const double vL = vm1 + 0.5 * lim_slope(vm1 - vm2, v0 - vm1, a.limiter);
       const double vR = v0 - 0.5 * lim_slope(v0 - vm1, vp1 - v0, a.limiter);
-      adL[q] = (F)((1.0 - E) * fmax(vL, 0.0));
-      adR[q] = (F)((1.0 - E) * fmin(vR, 0.0));
+      fc.aL = (F)((1.0 - E) * fmax(vL, 0.0));
+      fc.aR = (F)((1.0 - E) * fmin(vR, 0.0));
     }
+    return fc;
+  };
+  Face fcx[TZ], fcy[TZ], fcz[TZ + 1];
+#pragma unroll
+  for (int k = 0; k < TZ; ++k) {
+    fcx[k] = make_face(2, z0 + k, gy, gx);
+    fcy[k] = make_face(1, z0 + k, gy, gx);
   }
-
-  // ---- curved: the record word this thread stages every direction
-  const F* gsrc = nullptr;
-  long long gstride = 0;
-  if (CURVED && t < NREC * 4) {
-    const int rec = t >> 2, comp = t & 3;
-    if (rec < NRR) {
-      const int i1 = z0 + rec / TY, i2 = y0 + rec % TY;
-      if (i1 <= n1 && i2 < n2) {
-        gsrc = (const F*)p.rec_r_v + ((long long)i1 * n2 + i2) * 4 + comp;
-        gstride = (long long)(n1 + 1) * n2 * 4;
-      }
-    } else if (rec < NRR + NRT) {
-      const int r2 = rec - NRR, i1 = z0 + r2 / (TY + 1), i2 = y0 + r2 % (TY + 1);
-      if (i1 < n1 && i2 <= n2) {
-        gsrc = (const F*)p.rec_t_v + ((long long)i1 * (n2 + 1) + i2) * 4 + comp;
-        gstride = (long long)n1 * (n2 + 1) * 4;
-      }
-    } else {
-      const int r3 = rec - NRR - NRT, i1 = z0 + r3 / TY, i2 = y0 + r3 % TY;
-      if (i1 < n1 && i2 < n2) {
-        gsrc = (const F*)p.rec_p_v + ((long long)i1 * n2 + i2) * 4 + comp;
-        gstride = (long long)n1 * n2 * 4;
-      }
-    }
-  }
+#pragma unroll
+  for (int f = 0; f <= TZ; ++f) fcz[f] = make_face(0, z0 + f, gy, gx);
+  // extra faces: the x face above the tile's last column on (row ty, plane
+  // lane) for lanes < TZ; the y face above its last row on (column tx, plane
+  // ty) for waves ty < TZ
+  const bool xe = tx < TZ, ye = ty < TZ;
+  const Face fcxe = make_face(2, z0 + (tx % TZ), gy, x0 + TX);
+  const Face fcye = make_face(1, z0 + (ty % TZ), y0 + TY, gx);
 
   // ---- own-cell data used in the direction loop
   F bA[TZ], bB[TZ];                        // lazy map of the stage-2 base intensity
-  double u0[TZ], u1[TZ], u2[TZ], u3[TZ];   // moving fluid: tetrad-frame 4-velocity
-  double abh[TZ];                          // moving fluid: (alpha^a + alpha^s) h
+  double u0[MOVING ? TZ : 1], u1[MOVING ? TZ : 1], u2[MOVING ? TZ : 1], u3[MOVING ? TZ : 1];
+  double abh[MOVING ? TZ : 1];             // (alpha^a + alpha^s) h
   double nu0k[TZ];                         // n^0 = 1/lapse (1 when flat)
 #pragma unroll
   for (int k = 0; k < TZ; ++k) {
-    const long long c = own[k];
+    const long long c = own(k);
     bA[k] = F(1);
     bB[k] = F(0);
     if (STAGE2 && p.mapB) {
@@ -429,6 +394,31 @@ k_stage(StageArgs a, StagePtrs p) {
     }
     nu0k[k] = CURVED ? p.nu0[c / n3] : 1.0;
   }
+  // curved: the record word this thread stages every direction
+  const F* gsrc = nullptr;
+  long long gstride = 0;
+  if (CURVED && t < NREC * 4) {
+    const int rec = t >> 2, comp = t & 3;
+    if (rec < NRX) {  // phi rows (k, ty) and centre factors
+      const int i1 = z0 + rec / TY, i2 = y0 + rec % TY;
+      if (i1 < n1 && i2 < n2) {
+        gsrc = (const F*)p.rec_p_v + ((long long)i1 * n2 + i2) * 4 + comp;
+        gstride = (long long)n1 * n2 * 4;
+      }
+    } else if (rec < NRX + NRY) {  // theta faces (k, 0..TY)
+      const int r2 = rec - NRX, i1 = z0 + r2 / (TY + 1), i2 = y0 + r2 % (TY + 1);
+      if (i1 < n1 && i2 <= n2) {
+        gsrc = (const F*)p.rec_t_v + ((long long)i1 * (n2 + 1) + i2) * 4 + comp;
+        gstride = (long long)n1 * (n2 + 1) * 4;
+      }
+    } else {  // r faces (0..TZ, ty)
+      const int r3 = rec - NRX - NRY, i1 = z0 + r3 / TY, i2 = y0 + r3 % TY;
+      if (i1 <= n1 && i2 < n2) {
+        gsrc = (const F*)p.rec_r_v + ((long long)i1 * n2 + i2) * 4 + comp;
+        gstride = (long long)(n1 + 1) * n2 * 4;
+      }
+    }
+  }
 
   // accumulators: at rest E_- = sum w I~; moving E_-, A1, A2
   constexpr int NACC = MOVING ? 3 : 1;
@@ -441,151 +431,187 @@ k_stage(StageArgs a, StagePtrs p) {
   const F h = (F)a.h;
   const F idx0 = (F)a.inv_dx[0], idx1 = (F)a.inv_dx[1], idx2 = (F)a.inv_dx[2];
   const int ns = a.ns;
-
-  // prefetch of direction 0
-  S pre[NJ];
-  S prb[TZ];
-  S pda[CURVED ? TZ : 1];  // curved: angular divergence of the own cells
-  F gpre = F(0);
+  const F* __restrict__ dirF = (const F*)p.dirF_v;
   const S* angD = (const S*)p.angD_v;
+
+  // ---- prefetch of direction 0
+  S pw[NW], py[TZ], px, pb[TZ], pda[CURVED ? TZ : 1];
+  F gpre = F(0);
+  auto prefetch = [&](int s) {
+    const S* Is = Iflux + (long long)s * nc;
 #pragma unroll
-  for (int j = 0; j < NJ; ++j) pre[j] = Iflux[gidx[j]];
-  if (CURVED) {
-    if (gsrc) gpre = gsrc[0];
+    for (int j = 0; j < NW; ++j) pw[j] = Is[wcell[j]];
 #pragma unroll
-    for (int k = 0; k < TZ; ++k) pda[k] = angD[own[k]];
-  }
-  if (STAGE2) {
+    for (int k = 0; k < TZ; ++k) py[k] = Is[ycell[k]];
+    px = Is[xcell];
+    if (STAGE2) {
+      const S* Ib = Ibase + (long long)s * nc;
 #pragma unroll
-    for (int k = 0; k < TZ; ++k) prb[k] = Ibase[own[k]];
-  }
+      for (int k = 0; k < TZ; ++k) pb[k] = Ib[own(k)];
+    }
+    if (CURVED) {
+      if (gsrc) gpre = gsrc[(long long)s * gstride];
+      const S* As = angD + (long long)s * nc;
+#pragma unroll
+      for (int k = 0; k < TZ; ++k) pda[k] = As[own(k)];
+    }
+  };
+  prefetch(0);
 
   for (int s = 0; s < ns; ++s) {
     const int buf = s & 1;
-    F* R = reg[buf];
-    F* FL = flx[buf];
-    // direction components along i1 (z of the tile), i2 (y), i3 (x)
+    // direction components along i1 (z), i2 (y), i3 (x)
     const F nz = dirF[s], ny = dirF[ns + s], nx = dirF[2 * ns + s];
-    // zero-incoming: which outside sides receive zero for this direction
+    // flat zero-incoming: the outside sides that receive zero for this direction
     const unsigned inc = (nz > F(0) ? 1u : 0u) | (nz < F(0) ? 2u : 0u) | (ny > F(0) ? 4u : 0u) |
                          (ny < F(0) ? 8u : 0u) | (nx > F(0) ? 16u : 0u) | (nx < F(0) ? 32u : 0u);
-    // 1. stage the region (lazy map applied)
-    if (CURVED && anyzf) {
-      const unsigned char* zs = p.zin + (long long)s * a.zin_stride;
+    const unsigned char* zs = CURVED ? p.zin + (long long)s * a.zin_stride : nullptr;
+    auto ghost_zero = [&](unsigned flags6, int zoff) -> bool {
+      if (CURVED) return zoff >= 0 && zs[zoff] != 0;
+      return (flags6 & inc) != 0u;
+    };
+    // 1. column window in registers, own planes and halos to LDS
+    F w[NW];
 #pragma unroll
-      for (int j = 0; j < NJ; ++j)
-        R[t + j * NT] = (zoff[j] >= 0 && zs[zoff[j]]) ? F(0) : mA[j] * (F)pre[j] + mB[j];
-    } else if (anyzf) {
-#pragma unroll
-      for (int j = 0; j < NJ; ++j)
-        R[t + j * NT] = (slot_flags(j) & inc) ? F(0) : mA[j] * (F)pre[j] + mB[j];
-    } else {
-#pragma unroll
-      for (int j = 0; j < NJ; ++j) R[t + j * NT] = mA[j] * (F)pre[j] + mB[j];
+    for (int j = 0; j < NW; ++j) {
+      w[j] = wA[j] * (F)pw[j] + wB[j];
+      if (ghost_zero((unsigned)(wflag >> (6 * j)) & 63u, CURVED ? wzoff[j] : -1)) w[j] = F(0);
     }
-    F base[TZ];
-    if (STAGE2) {
 #pragma unroll
-      for (int k = 0; k < TZ; ++k) base[k] = bA[k] * (F)prb[k] + bB[k];
+    for (int k = 0; k < TZ; ++k) pl[buf][k][ty + 2][tx + 2] = w[k + 2];
+#pragma unroll
+    for (int k = 0; k < TZ; ++k) {
+      F v = yA[k] * (F)py[k] + yB[k];
+      if (ghost_zero((yflag >> (6 * k)) & 63u, CURVED ? yzoff[k] : -1)) v = F(0);
+      pl[buf][k][hry][tx + 2] = v;
     }
-    F dang[CURVED ? TZ : 1];
+    if (xh) {
+      F v = xA * (F)px + xB;
+      if (ghost_zero(xflag, xzoff)) v = F(0);
+      pl[buf][hk][ty + 2][hrx] = v;
+    }
+    F base[TZ], dang[CURVED ? TZ : 1];
+#pragma unroll
+    for (int k = 0; k < TZ; ++k) {
+      base[k] = STAGE2 ? bA[k] * (F)pb[k] + bB[k] : w[k + 2];
+      if (CURVED) dang[k] = (F)pda[k];
+    }
     F* GR = grec[CURVED ? buf : 0];
-    if (CURVED) {
-      if (t < NREC * 4) GR[t] = gpre;
-#pragma unroll
-      for (int k = 0; k < TZ; ++k) dang[k] = (F)pda[k];
-    }
+    if (CURVED && t < NREC * 4) GR[t] = gpre;
     __syncthreads();
-    // prefetch the next direction while this one is computed
-    if (s + 1 < ns) {
-      const S* Is = Iflux + (long long)(s + 1) * nc;
-#pragma unroll
-      for (int j = 0; j < NJ; ++j) pre[j] = Is[gidx[j]];
-      if (STAGE2) {
-        const S* Ib = Ibase + (long long)(s + 1) * nc;
-#pragma unroll
-        for (int k = 0; k < TZ; ++k) prb[k] = Ib[own[k]];
-      }
+    if (s + 1 < ns) prefetch(s + 1);
+
+    // 2. face fluxes.  With half slopes hL, hR either side of a face and the
+    // cell values vm1 | v0, the modified flux of Sec. 3.5 is
+    //   nu > 0:  nu (u (vm1 + hL) + v (v0 - hR) + d (vm1 - v0))
+    //   nu < 0:  nu (v (vm1 + hL) + u (v0 - hR) - d (vm1 - v0))
+    // plus the advection term aL (vm1 + hL) + aR (v0 - hR) for a moving fluid.
+    // curved: gP, gN (one of them zero) and gA from the face's record; flat:
+    // the sign of the direction component is uniform over a face group, so
+    // each group takes one branch (POS) with weight nu and advection weight 1
+    auto flux = [&](auto pos_tag, const Face& fc, F gP, F gN, F gA, F vm2, F vm1, F v0, F vp1) -> F {
+      constexpr int POS = decltype(pos_tag)::value;
+      const F hL = half_slope<LIM>(vm1 - vm2, v0 - vm1), hR = half_slope<LIM>(v0 - vm1, vp1 - v0);
+      const F L = vm1 + hL, Rr = v0 - hR, D = vm1 - v0;
+      F f;
+      if (CURVED)
+        f = gP * (fc.u * L + fc.v * Rr + fc.d * D) + gN * (fc.v * L + fc.u * Rr - fc.d * D);
+      else if (POS)
+        f = gP * (fc.u * L + fc.v * Rr + fc.d * D);
+      else
+        f = gP * (fc.v * L + fc.u * Rr - fc.d * D);
+      if (MOVING) f += gA * (fc.aL * L + fc.aR * Rr);
+      return f;
+    };
+    const F (*P)[RY][RX] = pl[buf];
+    // weights of a face from its record (curved) or the direction component
+    auto weights = [&](int rec, F nu, F& gP, F& gN, F& gA) {
       if (CURVED) {
-        if (gsrc) gpre = gsrc[(long long)(s + 1) * gstride];
-        const S* As = angD + (long long)(s + 1) * nc;
-#pragma unroll
-        for (int k = 0; k < TZ; ++k) pda[k] = As[own[k]];
-      }
-    }
-    // 2. face fluxes, each face once; the sign of the direction component is
-    // uniform over an axis, so each axis takes one branch per direction
-    auto faces = [&](auto axis_tag, F nu) {
-      constexpr int AX = decltype(axis_tag)::value;
-      constexpr int Q0 = AX == 2 ? 0 : (AX == 1 ? JX : JX + JY);
-      constexpr int QN = AX == 2 ? JX : (AX == 1 ? JY : JZ);
-      constexpr int ST = AX == 2 ? 1 : (AX == 1 ? RX : RX * RY);
-      // F = nu (P I_l + Q I_l+1 + U dL - V dR) for nu > 0, the mirror image for
-      // nu < 0; hL, hR are half slopes, so U2 = 2U and V2 = 2V multiply them
-      auto one = [&](int q, bool pos) {
-        const F* Rq = R + fr0[q];
-        const F vm2 = Rq[-2 * ST], vm1 = Rq[-ST], v0 = Rq[0], vp1 = Rq[ST];
-        const F d0 = vm1 - vm2, d1 = v0 - vm1, d2 = vp1 - v0;
-        const F hL = half_slope<LIM>(d0, d1), hR = half_slope<LIM>(d1, d2);
-        const FaceC<F>& c = fc[q];
-        F fl = pos ? nu * (c.P * vm1 + c.Q * v0 + c.U * hL - c.V * hR)
-                   : nu * (c.Q * vm1 + c.P * v0 + c.V * hL - c.U * hR);
-        if (MOVING) fl += adL[q] * (vm1 + hL) + adR[q] * (v0 - hR);
-        FL[t + q * NT] = fl;
-      };
-      if (__builtin_amdgcn_readfirstlane(__float_as_int((float)nu)) > 0) {
-#pragma unroll
-        for (int qq = 0; qq < QN; ++qq) one(Q0 + qq, true);
+        const F* r = GR + rec * 4;
+        gP = r[0];
+        gN = r[1];
+        gA = r[2];
       } else {
-#pragma unroll
-        for (int qq = 0; qq < QN; ++qq) one(Q0 + qq, false);
+        gP = nu;
+        gN = F(0);
+        gA = F(1);
       }
     };
-    if (CURVED) {
-      // direction components vary with position: both upwind forms, weighted
-      // by the face records (one of gP, gN is zero)
+    F fz[TZ + 1];
+    auto xfaces = [&](auto pos) {
+      // x faces below each own cell; the extra one above the last column
 #pragma unroll
-      for (int q = 0; q < JF; ++q) {
-        const int ST = q < JX ? 1 : (q < JX + JY ? RX : RX * RY);
-        const F* Rq = R + fr0[q];
-        const F vm2 = Rq[-2 * ST], vm1 = Rq[-ST], v0 = Rq[0], vp1 = Rq[ST];
-        const F d0 = vm1 - vm2, d1 = v0 - vm1, d2 = vp1 - v0;
-        const F hL = half_slope<LIM>(d0, d1), hR = half_slope<LIM>(d1, d2);
-        const F* g = GR + frec[q] * 4;
-        const FaceC<F>& c = fc[q];
-        F fl = g[0] * (c.P * vm1 + c.Q * v0 + c.U * hL - c.V * hR) +
-               g[1] * (c.Q * vm1 + c.P * v0 + c.V * hL - c.U * hR);
-        if (MOVING) fl += g[2] * (adL[q] * (vm1 + hL) + adR[q] * (v0 - hR));
-        FL[t + q * NT] = fl;
+      for (int k = 0; k < TZ; ++k) {
+        F gP, gN, gA;
+        weights(k * TY + ty, nx, gP, gN, gA);
+        fxs[buf][k][ty][tx] = flux(pos, fcx[k], gP, gN, gA, P[k][ty + 2][tx], P[k][ty + 2][tx + 1],
+                                   w[k + 2], P[k][ty + 2][tx + 3]);
       }
+      if (xe) {
+        const int k = tx % TZ;
+        F gP, gN, gA;
+        weights(k * TY + ty, nx, gP, gN, gA);
+        fxs[buf][k][ty][TX] = flux(pos, fcxe, gP, gN, gA, P[k][ty + 2][TX], P[k][ty + 2][TX + 1],
+                                   P[k][ty + 2][TX + 2], P[k][ty + 2][TX + 3]);
+      }
+    };
+    auto yfaces = [&](auto pos) {
+      // y faces below each own cell; the extra one above the last row
+#pragma unroll
+      for (int k = 0; k < TZ; ++k) {
+        F gP, gN, gA;
+        weights(NRX + k * (TY + 1) + ty, ny, gP, gN, gA);
+        fys[buf][k][ty][tx] = flux(pos, fcy[k], gP, gN, gA, P[k][ty][tx + 2], P[k][ty + 1][tx + 2],
+                                   w[k + 2], P[k][ty + 3][tx + 2]);
+      }
+      if (ye) {
+        const int k = ty % TZ;
+        F gP, gN, gA;
+        weights(NRX + k * (TY + 1) + TY, ny, gP, gN, gA);
+        fys[buf][k][TY][tx] = flux(pos, fcye, gP, gN, gA, P[k][TY][tx + 2], P[k][TY + 1][tx + 2],
+                                   P[k][TY + 2][tx + 2], P[k][TY + 3][tx + 2]);
+      }
+    };
+    auto zfaces = [&](auto pos) {
+      // z faces of the column, from registers
+#pragma unroll
+      for (int f = 0; f <= TZ; ++f) {
+        F gP, gN, gA;
+        weights(NRX + NRY + f * TY + ty, nz, gP, gN, gA);
+        fz[f] = flux(pos, fcz[f], gP, gN, gA, w[f], w[f + 1], w[f + 2], w[f + 3]);
+      }
+    };
+    using TPos = std::integral_constant<int, 1>;
+    using TNeg = std::integral_constant<int, 0>;
+    if (CURVED) {
+      xfaces(TPos{});
+      yfaces(TPos{});
+      zfaces(TPos{});
     } else {
-      faces(std::integral_constant<int, 2>{}, nx);
-      faces(std::integral_constant<int, 1>{}, ny);
-      faces(std::integral_constant<int, 0>{}, nz);
+      auto up = [](F nu) { return __builtin_amdgcn_readfirstlane(nu > F(0) ? 1 : 0) != 0; };
+      if (up(nx)) xfaces(TPos{}); else xfaces(TNeg{});
+      if (up(ny)) yfaces(TPos{}); else yfaces(TNeg{});
+      if (up(nz)) zfaces(TPos{}); else zfaces(TNeg{});
     }
     __syncthreads();
+
     // 3. divergence, update, interaction sums
     const double ws = p.w[s];
 #pragma unroll
     for (int k = 0; k < TZ; ++k) {
-      const F fxl = FL[(k * TY + ty) * (TX + 1) + tx], fxh = FL[(k * TY + ty) * (TX + 1) + tx + 1];
-      const F fyl = FL[OFY + (k * (TY + 1) + ty) * TX + tx];
-      const F fyh = FL[OFY + (k * (TY + 1) + ty + 1) * TX + tx];
-      const F fzl = FL[OFZ + (k * TY + ty) * TX + tx];
-      const F fzh = FL[OFZ + ((k + 1) * TY + ty) * TX + tx];
-      const F bse = STAGE2 ? base[k] : R[((k + 2) * RY + ty + 2) * RX + tx + 2];
+      const F dx = fxs[buf][k][ty][tx + 1] - fxs[buf][k][ty][tx];
+      const F dy = fys[buf][k][ty + 1][tx] - fys[buf][k][ty][tx];
+      const F dz = fz[k + 1] - fz[k];
       F It;
       if (CURVED) {
         // X = n^0 n_0 I updated by the area-weighted face fluxes; x = 1/(dV n^0 n_0),
         // zero where |n_0| is below the cut (I~ = 0 there)
-        const F x = GR[(NRR + NRT + k * TY + ty) * 4 + 3];
-        const F sum = (fzh - fzl) + (fyh - fyl) + (fxh - fxl);
-        It = (x != F(0) ? bse : F(0)) - h * (x * sum + dang[k]);
+        const F x = GR[(k * TY + ty) * 4 + 3];
+        It = (x != F(0) ? base[k] : F(0)) - h * (x * (dz + dy + dx) + dang[k]);
       } else {
-        const F div = (fzh - fzl) * idx0 + (fyh - fyl) * idx1 + (fxh - fxl) * idx2;
-        It = bse - h * div;
+        It = base[k] - h * (dz * idx0 + dy * idx1 + dx * idx2);
       }
-      if (valid[k]) Iout[(long long)s * nc + own[k]] = (S)It;
+      if (valid[k]) Iout[(long long)s * nc + own(k)] = (S)It;
       // ---- interaction sums (FP64)
       const double Itd = (double)(S)It;
       if (MOVING) {
@@ -606,7 +632,7 @@ k_stage(StageArgs a, StagePtrs p) {
 #pragma unroll
   for (int k = 0; k < TZ; ++k) {
     if (!valid[k]) continue;
-    const long long c = own[k];
+    const long long c = own(k);
     double aak, ask;
     opac(a, p.rho, p.Tcoef, p.ka, p.ks, c, aak, ask);
     const double ab = aak + ask, rrk = p.rho[c], T0k = p.Tstart[c];
@@ -738,32 +764,88 @@ k_materialize(long long nc, int ns, double h, const double* __restrict__ map, S*
 // launchers
 // ---------------------------------------------------------------------------
 namespace {
-template <typename S, typename F, int TY, int TZ, int LIM>
+// Order the tiles so that the tiles of one XCD that are resident together form
+// a compact brick: a tile's halo planes then come from L2 (the neighbouring
+// tiles stage the same direction at about the same time) instead of HBM.
+// The order is a permutation of the tiles; codes pack (tx, ty, tz).
+hipError_t tile_order(rt_ctx* c, int tx, int ty, int tz, int TYc, int TZc, int resident,
+                      const unsigned** out) {
+  *out = nullptr;
+  if (tx > 1024 || ty > 2048 || tz > 2048) return hipSuccess;  // natural order
+  const long long key = (((long long)tx * 4096 + ty) * 4096 + tz) * 64 * 64 +
+                        (long long)(TYc * 8 + TZc) * 64 + std::min(resident, 63);
+  if (key != c->tile_order_key) {
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) == hipSuccess)
+      (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    const int conc = std::max(1, cus / 8 * resident);  // tiles in flight per XCD
+    const int GX = std::min(tx, 2);
+    int GY = 1, GZ = 1;
+    double best = 1e30;
+    for (int gy = 1; gy <= ty; ++gy) {
+      const int gz = std::max(1, std::min(tz, conc / (GX * gy)));
+      const double aspect = std::fabs(std::log((double)(gy * TYc) / (gz * TZc)));
+      const double fill = std::fabs(std::log((double)(GX * gy * gz) / conc));
+      if (aspect + 2.0 * fill < best) {
+        best = aspect + 2.0 * fill;
+        GY = gy;
+        GZ = gz;
+      }
+    }
+    std::vector<unsigned> ord;
+    ord.reserve((size_t)tx * ty * tz);
+    for (int z0 = 0; z0 < tz; z0 += GZ)
+      for (int y0 = 0; y0 < ty; y0 += GY)
+        for (int x0 = 0; x0 < tx; x0 += GX)
+          for (int z = z0; z < std::min(tz, z0 + GZ); ++z)
+            for (int y = y0; y < std::min(ty, y0 + GY); ++y)
+              for (int x = x0; x < std::min(tx, x0 + GX); ++x)
+                ord.push_back((unsigned)x | ((unsigned)y << 10) | ((unsigned)z << 21));
+    if (c->d_tile_order) (void)hipFree(c->d_tile_order);
+    c->d_tile_order = nullptr;
+    c->tile_order_key = -1;
+    hipError_t e = hipMalloc((void**)&c->d_tile_order, ord.size() * sizeof(unsigned));
+    if (e != hipSuccess) return e;
+    e = hipMemcpy(c->d_tile_order, ord.data(), ord.size() * sizeof(unsigned), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return e;
+    c->tile_order_key = key;
+  }
+  *out = c->d_tile_order;
+  return hipSuccess;
+}
+
+template <typename Kern>
+hipError_t launch_ordered(rt_ctx* c, Kern kern, StageArgs a, StagePtrs p, int TYc, int TZc,
+                          hipStream_t st) {
+  int resident = 1;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&resident, reinterpret_cast<const void*>(kern),
+                                                   TX * TYc, 0) != hipSuccess)
+    resident = 1;
+  hipError_t e = tile_order(c, a.tiles_x, a.tiles_y, a.tiles_z, TYc, TZc, std::max(resident, 1),
+                            &p.tile_order);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(kern, dim3(8 * a.tiles_per_xcd), dim3(TX * TYc), 0, st, a, p);
+  return hipGetLastError();
+}
+
+template <typename S, typename F, int TZ, int LIM>
 hipError_t launch_tiled(rt_ctx* c, StageArgs a, const StagePtrs& p, bool stage2, hipStream_t st) {
+  constexpr int TY = 4;
   a.tiles_x = (c->n[2] + TX - 1) / TX;
   a.tiles_y = (c->n[1] + TY - 1) / TY;
   a.tiles_z = (c->n[0] + TZ - 1) / TZ;
   a.ntiles = a.tiles_x * a.tiles_y * a.tiles_z;
   a.tiles_per_xcd = (a.ntiles + 7) / 8;
-  dim3 grid(8 * a.tiles_per_xcd), block(TX * TY);
   if (c->curved) {
     // curved geometry always runs the moving-fluid form (direction-dependent map)
-    if (stage2)
-      hipLaunchKernelGGL((k_stage<S, F, TY, TZ, true, true, LIM, true>), grid, block, 0, st, a, p);
-    else
-      hipLaunchKernelGGL((k_stage<S, F, TY, TZ, false, true, LIM, true>), grid, block, 0, st, a, p);
-  } else if (c->moving) {
-    if (stage2)
-      hipLaunchKernelGGL((k_stage<S, F, TY, TZ, true, true, LIM, false>), grid, block, 0, st, a, p);
-    else
-      hipLaunchKernelGGL((k_stage<S, F, TY, TZ, false, true, LIM, false>), grid, block, 0, st, a, p);
-  } else {
-    if (stage2)
-      hipLaunchKernelGGL((k_stage<S, F, TY, TZ, true, false, LIM, false>), grid, block, 0, st, a, p);
-    else
-      hipLaunchKernelGGL((k_stage<S, F, TY, TZ, false, false, LIM, false>), grid, block, 0, st, a, p);
+    return stage2 ? launch_ordered(c, k_stage<S, F, TZ, true, true, LIM, true>, a, p, TY, TZ, st)
+                  : launch_ordered(c, k_stage<S, F, TZ, false, true, LIM, true>, a, p, TY, TZ, st);
   }
-  return hipGetLastError();
+  if (c->moving)
+    return stage2 ? launch_ordered(c, k_stage<S, F, TZ, true, true, LIM, false>, a, p, TY, TZ, st)
+                  : launch_ordered(c, k_stage<S, F, TZ, false, true, LIM, false>, a, p, TY, TZ, st);
+  return stage2 ? launch_ordered(c, k_stage<S, F, TZ, true, false, LIM, false>, a, p, TY, TZ, st)
+                : launch_ordered(c, k_stage<S, F, TZ, false, false, LIM, false>, a, p, TY, TZ, st);
 }
 }  // namespace
 
@@ -771,10 +853,10 @@ hipError_t launch_stage(rt_ctx* c, const StageArgs& a, const StagePtrs& p, bool 
                         hipStream_t st) {
   const bool mc = a.limiter == RT_LIM_MC;
   if (c->fp32)
-    return mc ? launch_tiled<float, float, 4, 2, RT_LIM_MC>(c, a, p, stage2, st)
-              : launch_tiled<float, float, 4, 2, RT_LIM_MINMOD>(c, a, p, stage2, st);
-  return mc ? launch_tiled<double, double, 4, 1, RT_LIM_MC>(c, a, p, stage2, st)
-            : launch_tiled<double, double, 4, 1, RT_LIM_MINMOD>(c, a, p, stage2, st);
+    return mc ? launch_tiled<float, float, 4, RT_LIM_MC>(c, a, p, stage2, st)
+              : launch_tiled<float, float, 4, RT_LIM_MINMOD>(c, a, p, stage2, st);
+  return mc ? launch_tiled<double, double, 2, RT_LIM_MC>(c, a, p, stage2, st)
+            : launch_tiled<double, double, 2, RT_LIM_MINMOD>(c, a, p, stage2, st);
 }
 
 hipError_t launch_materialize(rt_ctx* c, void* I, const double* map, double h, double* R,

@@ -61,6 +61,9 @@ struct StagePtrs {
   const unsigned char* zin;
   const void* angD_v;
   const double* nu0;
+  // tile launch order: code = tx | ty << 10 | tz << 21 per position in the
+  // order (NULL: x fastest, then y, then z)
+  const unsigned* tile_order;
 };
 
 hipError_t launch_stage(rt_ctx* c, const StageArgs& a, const StagePtrs& p, bool stage2,
