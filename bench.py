@@ -1,8 +1,8 @@
 """Throughput of the gray transfer step on one MI355X.
 
 One benchmark step is one pass of the whole hot path over the workload:
-rt_step (two transport stages, two implicit interactions) followed by
-rt_moments (R^(ab) of the new intensity).  Workload: flat 128^3 cells x 162
+one rt_step call advancing one step (two transport stages, two implicit
+interactions) that also returns R^(ab) of the new intensity and the 4-force.  Workload: flat 128^3 cells x 162
 directions (geodesic generation 2), lognormal density (sigma_ln = 1, k^-2
 random field), T ~ U[0.5, 2], alpha^a = rho^2 T^-3.5, alpha^s = rho, Method 2,
 periodic, dt = 0.4; synthetic inputs from `workloads`, resident in HBM before
@@ -62,7 +62,8 @@ def make_inputs(wl, ctx, torch):
         I0 = T ** 4 / (4 * math.pi)
     I = I0.reshape(1, -1).expand(ctx.ns, -1).to(ctx.intensity_dtype).contiguous()
     R = torch.empty((10, ctx.nc), dtype=torch.float64, device=dev)
-    return (rho, u), I, T, R
+    G = torch.empty((4, ctx.nc), dtype=torch.float64, device=dev)
+    return (rho, u, G), I, T, R
 
 
 def make_context(wl, precision, P):
@@ -82,9 +83,10 @@ def run_form(wl, precision, steps, warmup, torch, P, per_call=False):
     """Time `steps` steps of rt_step (moments of every step written to R);
     either one call advancing all steps, or one call per step."""
     ctx, dt = make_context(wl, precision, P)
-    rho, I, T, R = make_inputs(wl, ctx, torch)
+    keep, I, T, R = make_inputs(wl, ctx, torch)
+    G = keep[2]
     for _ in range(warmup):
-        ctx.step(I, T, dt, 1, R=R)
+        ctx.step(I, T, dt, 1, G=G, R=R)
     torch.cuda.synchronize()
     ctx.set_debug(2)                      # HIP events around every launch
     ctx.kernel_times()                    # reset the tally
@@ -92,9 +94,9 @@ def run_form(wl, precision, steps, warmup, torch, P, per_call=False):
     t0 = time.perf_counter()
     if per_call:
         for _ in range(steps):
-            ctx.step(I, T, dt, 1, R=R)
+            ctx.step(I, T, dt, 1, G=G, R=R)
     else:
-        ctx.step(I, T, dt, steps, R=R)
+        ctx.step(I, T, dt, steps, G=G, R=R)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ktimes = ctx.kernel_times()
@@ -102,7 +104,7 @@ def run_form(wl, precision, steps, warmup, torch, P, per_call=False):
     ok = bool(torch.isfinite(R).all().item()) and bool(torch.isfinite(T).all().item())
     ns, nc = ctx.ns, ctx.nc
     ctx.close()
-    del I, T, R, rho
+    del I, T, R, G, keep
     torch.cuda.empty_cache()
     return dict(wall=wall, ktimes=ktimes, ns=ns, nc=nc, finite=ok,
                 elem=4 if precision == "fp32" else 8)
@@ -160,7 +162,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--forms", default="fp32,fp64")
-    ap.add_argument("--no-per-call", action="store_true")
+    ap.add_argument("--no-per-call", action="store_true",
+                    help="skip the extra line with K steps advanced by one rt_step call")
     ap.add_argument("--no-torus", action="store_true",
                     help="skip the Kerr-Schild torus line (256x128x64 x 162, FP32)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -193,11 +196,11 @@ def main():
     for prec in forms:
         print(f"bench: {prec} 128^3 x 162, {args.warmup} warmup + {args.steps} timed steps",
               file=sys.stderr, flush=True)
-        res[prec] = run_form(wl, prec, args.steps, args.warmup, torch, P)
-    per_call = None
+        res[prec] = run_form(wl, prec, args.steps, args.warmup, torch, P, per_call=True)
+    multi = None
     if not args.no_per_call and "fp32" in forms:
-        print("bench: fp32, one rt_step call per step", file=sys.stderr, flush=True)
-        per_call = run_form(wl, "fp32", args.steps, args.warmup, torch, P, per_call=True)
+        print("bench: fp32, all timed steps in one rt_step call", file=sys.stderr, flush=True)
+        multi = run_form(wl, "fp32", args.steps, args.warmup, torch, P)
     head = "fp32" if "fp32" in res else forms[0]
     r = res[head]
     cd_per_step = r["ns"] * r["nc"]
@@ -229,8 +232,8 @@ def main():
                                "T~U[0.5,2], alpha^a=rho^2 T^-3.5, alpha^s=rho, Method 2, periodic",
                    "form": "fp32 transport + fp64 interaction/moments" if head == "fp32" else "fp64",
                    "cells": r["nc"], "directions": r["ns"],
-                   "step": "predictor-corrector step incl. R^(ab) of the new intensity; "
-                           "K steps advanced by one rt_step call",
+                   "step": "one rt_step call per step: predictor-corrector step incl. R^(ab) "
+                           "and the 4-force of the new intensity",
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": dom,
@@ -243,16 +246,17 @@ def main():
         out[f"ms_per_step_{prec}"] = 1e3 * rr["wall"] / args.steps
         if not rr["finite"]:
             out["error"] = f"non-finite moments in the {prec} run"
-    if per_call is not None:
-        out["value_fp32_one_call_per_step"] = per_call["ns"] * per_call["nc"] * args.steps / per_call["wall"]
-        out["ms_per_step_fp32_one_call_per_step"] = 1e3 * per_call["wall"] / args.steps
+    if multi is not None:
+        # the interaction map of intermediate steps stays lazy, R only for the last
+        out["value_fp32_k_steps_one_call"] = multi["ns"] * multi["nc"] * args.steps / multi["wall"]
+        out["ms_per_step_fp32_k_steps_one_call"] = 1e3 * multi["wall"] / args.steps
     if "fp32" in res and "fp64" in res:
         out["speedup_fp32_over_fp64"] = out["value_fp32"] / out["value_fp64"]
     if not args.no_torus:
         # curved geometry: the a = 0.9 Kerr-Schild torus, FP32 transport form
         print("bench: torus_ks fp32 256x128x64 x 162", file=sys.stderr, flush=True)
         tw = W.torus_ks()
-        tr = run_form(tw, "fp32", args.steps, args.warmup, torch, P)
+        tr = run_form(tw, "fp32", args.steps, args.warmup, torch, P, per_call=True)
         out["torus_ks"] = {
             "workload": "Kerr-Schild a=0.9 torus, (ln r, theta, phi) 256x128x64 x 162 directions, "
                         "Keplerian flow, Method 2, FP32 transport",

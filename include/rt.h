@@ -5,7 +5,8 @@
  * geodesic angular grid in a fixed (stationary) metric, as in arXiv
  * 2508.15532 (Wallace, Begue, Pe'er): the finite-volume transport of the
  * covariant transfer equation (Sec. 3.1, Eq. radiative_transfer_discrete;
- * fluxes of Sec. 3.5), the implicit radiation-fluid interaction (Sec. 3.6.2,
+ * spatial fluxes of Sec. 3.5; in curved space the angular fluxes between
+ * directions of Sec. 2.2 and 3.5), the implicit radiation-fluid interaction (Sec. 3.6.2,
  * Eq. fluid_interaction_discrete and the temperature equations), the
  * predictor-corrector step (Sec. 3.7), and the moments R^(ab) = int n^a n^b I
  * dOmega (Eq. R).  Units are scale free: c = G = a_rad = k_B/(mu m_p) = 1.
@@ -76,10 +77,10 @@ enum { RT_OPAC_KIRCHHOFF_CONST = 0, RT_OPAC_BREMS = 1, RT_OPAC_FIXED_EMISSIVITY 
 enum { RT_TETRAD = 0, RT_COORD = 1 };
 
 typedef struct {
-  int n[3];            /* cells per axis (>= 1) */
+  int n[3];            /* cells per axis (>= 1); at most 2^31 - 1 cells in total */
   double xlo[3];       /* logical lower bounds */
   double xhi[3];       /* logical upper bounds (> xlo) */
-  int coords;          /* RT_CART or RT_LOGR_THETA_PHI (x1 = ln r) */
+  int coords;          /* RT_CART or RT_LOGR_THETA_PHI (x1 = ln r, theta in [0, pi]) */
   int bc_lo[3];        /* RT_BC_* per axis; periodic must be set on both sides */
   int bc_hi[3];
   int generation;      /* geodesic generation g in 0..5: Ns = 10*4^g + 2 */
@@ -89,8 +90,10 @@ typedef struct {
   int angular_recon;   /* reserved (0): donor-cell angular states */
   double abar;         /* coefficient in tau = abar alpha-hat dt (Sec. 3.5); 1 */
   double rho_floor;    /* no interaction below this density (Sec. 3.8); 5e-4 */
-  double n0_cut;       /* |n_0| below which I is zeroed (Sec. 3.5); 0.1 */
-  int pole_zero_rows;  /* rows next to each pole with I zeroed (curved grids) */
+  double n0_cut;       /* |n_0| below which I is zeroed (Sec. 3.5, curved only); 0.1 */
+  int pole_zero_rows;  /* theta rows next to each pole whose I is zeroed after each
+                          interaction (RT_LOGR_THETA_PHI only, 0..n[1]/2; 4 in the
+                          torus setup of Sec. 5); must be 0 for RT_CART */
 } rt_grid_desc;
 
 typedef struct {
@@ -98,7 +101,8 @@ typedef struct {
   double gamma;        /* adiabatic index (> 1) */
   double C_a, C_s;     /* coefficients of the BREMS model */
   const double* rho;   /* [Nc] mass density (required) */
-  const double* u;     /* [4][Nc] coordinate-frame fluid 4-velocity u^mu; NULL: at rest */
+  const double* u;     /* [4][Nc] coordinate-frame fluid 4-velocity u^mu; NULL: at rest
+                          (flat), the normal observer (Kerr-Schild) */
   const double* kappa_a; /* [Nc] absorption opacity (KIRCHHOFF_CONST, FIXED_EMISSIVITY); NULL: 0 */
   const double* kappa_s; /* [Nc] scattering opacity; NULL: 0 */
   const double* j;     /* [Nc] fluid-frame gray emissivity (FIXED_EMISSIVITY); NULL: 0 */
@@ -129,7 +133,16 @@ rt_status rt_grid_info(const rt_ctx* ctx, int* n_dirs, double* dirs_host, double
                        double* area_host);
 
 /* Set the stationary metric and tetrads (Sec. 2.1.1) and build the geometry
-   tables.  kind = RT_FLAT needs coords RT_CART (identity tetrad).
+   tables (host, once per context; a second call returns RT_E_STATE).
+   kind = RT_FLAT needs coords RT_CART (identity tetrad; M, a ignored).
+   kind = RT_KERR_SCHILD needs coords RT_LOGR_THETA_PHI: the Kerr metric of
+   mass M >= 0 and spin |a| <= M in Kerr-Schild coordinates with x1 = ln r
+   (M = 0, a = 0 is flat space in spherical coordinates); the tetrad's time leg
+   is the normal observer and its spatial legs come from Gram-Schmidt of
+   (d_phi, d_theta, d_x1) -> (3, 2, 1); the rotation coefficients that drive the
+   angular fluxes (Sec. 2.2) use fourth-order central differences of the
+   analytic tetrad (step 1e-3), so theta cell centres must lie more than 2e-3
+   from the axis.
    Returns in *dt_max_out (may be NULL) the largest admissible step:
    cfl * min over cells and axes of dx^a / max_s |n^a_s / n^0_s| (Sec. 3.8). */
 rt_status rt_set_metric(rt_ctx* ctx, int kind, double M, double a, double cfl, double* dt_max_out);
@@ -147,22 +160,24 @@ rt_status rt_set_opacities(rt_ctx* ctx, const rt_opacity_desc* desc, hipStream_t
    I     in/out [Ns][Nc] (element type per precision), T in/out [Nc].
    G_out optional [4][Nc]: tetrad-frame 4-force on the fluid of the last
          step's second interaction, -(R^(0a)(after) - R^(0a)(before))/dt.
-   R_out optional [10][Nc]: moments (as rt_moments, tetrad frame) of the new
-         intensity, computed inside every step from the FP64 interaction
-         state; on return it holds those of the last step.
+   R_out optional [10][Nc]: moments (as rt_moments, tetrad frame, FP64 sums of
+         the stored intensity) of the intensity returned, i.e. of the last
+         step; computed in the pass that applies the last interaction.
    0 < dt <= dt_max of rt_set_metric, else RT_E_ARG. */
 rt_status rt_step(rt_ctx* ctx, void* I, double* T, double dt, int nsteps, double* G_out,
                   double* R_out, hipStream_t stream);
 
 /* Moments (Eq. R): R[k][c] = sum_s w_s n^a n^b I[s][c] for the 10 pairs
    (a,b) = 00,01,02,03,11,12,13,22,23,33 (n^0 = 1), accumulated in FP64.
-   frame RT_COORD returns e^mu_a e^nu_b R^(ab) instead (identity when flat).
-   J optional [Nc]: R^00 / (4 pi). */
+   frame RT_COORD returns e^mu_a e^nu_b R^(ab) instead (identity when flat;
+   coordinate indices (t, x1, x2, x3) in the same storage order).
+   J optional [Nc]: R-hat^00 / (4 pi). */
 rt_status rt_moments(rt_ctx* ctx, const void* I, double* R, double* J, int frame,
                      hipStream_t stream);
 
 /* Adjoint of one rt_step step (nsteps = 1) for the FIXED_EMISSIVITY model
-   (temperature-independent opacities): given I^n and the loss gradient
+   (temperature-independent opacities), flat metric, fluid at rest (other
+   configurations return RT_E_ARG): given I^n and the loss gradient
    gI_np1 = dL/dI^(n+1), writes gI_n = dL/dI^n (may alias gI_np1) and ADDS
    dL/dkappa_a and dL/dj of this step into g_kappa_a, g_j ([Nc] each, either
    may be NULL).  T_n is read only. */
@@ -181,7 +196,7 @@ rt_status rt_set_debug(rt_ctx* ctx, int flags);
    (counts[k]) and their summed duration in milliseconds (ms[k]) since the
    previous call, then starts a new tally.  Either output may be NULL. */
 enum { RT_K_STAGE1 = 0, RT_K_STAGE2, RT_K_MATERIALIZE, RT_K_MOMENTS, RT_K_ADJOINT,
-       RT_K_ANGULAR, RT_NKERNELS };
+       RT_K_ANGULAR /* curved: angular flux divergence before each stage */, RT_NKERNELS };
 rt_status rt_kernel_times(rt_ctx* ctx, int* counts, double* ms);
 
 /* Number of interaction failures counted since the last call (debug mode). */

@@ -760,6 +760,73 @@ k_materialize(long long nc, int ns, double h, const double* __restrict__ map, S*
     for (int m = 0; m < 4; ++m) Gout[m * nc + c] = -g[m] / h;
 }
 
+// At-rest materialisation with two neighbouring cells per thread (vector
+// loads and stores of the pair, four directions in flight), optionally with
+// the moments and the 4-force of the new intensity.  nc must be even.
+template <typename S, bool MOM>
+__global__ void __launch_bounds__(256)
+k_materialize_pair(long long nc, int ns, double h, const double* __restrict__ map,
+                   S* __restrict__ I, const double* __restrict__ W16,
+                   double* __restrict__ Rout, double* __restrict__ Gout) {
+  using V2 = typename std::conditional<std::is_same<S, float>::value, float2, double2>::type;
+  const long long c = 2 * ((long long)blockIdx.x * blockDim.x + threadIdx.x);
+  if (c >= nc) return;
+  const double al0 = map[c], al1 = map[c + 1], be0 = map[nc + c], be1 = map[nc + c + 1];
+  double R0[MOM ? 10 : 1], R1[MOM ? 10 : 1], g0[MOM ? 4 : 1], g1[MOM ? 4 : 1];
+  if (MOM) {
+#pragma unroll
+    for (int m = 0; m < 10; ++m) R0[m] = R1[m] = 0.0;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) g0[m] = g1[m] = 0.0;
+  }
+  V2* q = reinterpret_cast<V2*>(I + c);
+  const long long stride = nc / 2;
+  // batches of B directions: all loads of a batch are issued before its stores
+  // (different directions never alias, which the compiler cannot see)
+  constexpr int B = 8;
+  for (int s0 = 0; s0 < ns; s0 += B) {
+    V2 v[B];
+#pragma unroll
+    for (int u = 0; u < B; ++u) v[u] = q[(long long)min(s0 + u, ns - 1) * stride];
+#pragma unroll
+    for (int u = 0; u < B; ++u) {
+      const int s = s0 + u;
+      if (s >= ns) break;
+      const double t0 = (double)v[u].x, t1 = (double)v[u].y;
+      V2 o;
+      o.x = (S)(al0 * t0 + be0);
+      o.y = (S)(al1 * t1 + be1);
+      q[(long long)s * stride] = o;
+      if (MOM) {
+        const double o0 = (double)o.x, o1 = (double)o.y;
+        const double* Ws = W16 + s * 16;
+#pragma unroll
+        for (int m = 0; m < 10; ++m) {
+          R0[m] += Ws[m] * o0;
+          R1[m] += Ws[m] * o1;
+        }
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+          g0[m] += Ws[m] * (o0 - t0);
+          g1[m] += Ws[m] * (o1 - t1);
+        }
+      }
+    }
+  }
+  if (MOM) {
+    if (Rout)
+      for (int m = 0; m < 10; ++m) {
+        Rout[m * nc + c] = R0[m];
+        Rout[m * nc + c + 1] = R1[m];
+      }
+    if (Gout)
+      for (int m = 0; m < 4; ++m) {
+        Gout[m * nc + c] = -g0[m] / h;
+        Gout[m * nc + c + 1] = -g1[m] / h;
+      }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
@@ -862,6 +929,26 @@ hipError_t launch_stage(rt_ctx* c, const StageArgs& a, const StagePtrs& p, bool 
 hipError_t launch_materialize(rt_ctx* c, void* I, const double* map, double h, double* R,
                               double* G, hipStream_t st) {
   dim3 grid((unsigned)((c->nc + 255) / 256)), block(256);
+  if (!c->moving && c->nc % 2 == 0) {
+    const dim3 g2((unsigned)((c->nc / 2 + 255) / 256));
+    const bool mom = R || G;
+    if (c->fp32) {
+      if (mom)
+        hipLaunchKernelGGL((k_materialize_pair<float, true>), g2, block, 0, st, c->nc, c->ns, h, map,
+                           (float*)I, c->d_W16, R, G);
+      else
+        hipLaunchKernelGGL((k_materialize_pair<float, false>), g2, block, 0, st, c->nc, c->ns, h, map,
+                           (float*)I, c->d_W16, R, G);
+    } else {
+      if (mom)
+        hipLaunchKernelGGL((k_materialize_pair<double, true>), g2, block, 0, st, c->nc, c->ns, h, map,
+                           (double*)I, c->d_W16, R, G);
+      else
+        hipLaunchKernelGGL((k_materialize_pair<double, false>), g2, block, 0, st, c->nc, c->ns, h, map,
+                           (double*)I, c->d_W16, R, G);
+    }
+    return hipGetLastError();
+  }
   if (c->fp32) {
     if (c->moving)
       hipLaunchKernelGGL((k_materialize<float, true>), grid, block, 0, st, c->nc, c->ns, h, map,
