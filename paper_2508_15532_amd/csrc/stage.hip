@@ -204,9 +204,15 @@ k_stage(StageArgs a, StagePtrs p) {
   constexpr int NRX = TZ * TY, NRY = TZ * (TY + 1), NRZ = (TZ + 1) * TY;
   constexpr int NREC = NRX + NRY + NRZ;
   static_assert(!CURVED || NREC * 4 <= NT, "one record word per thread");
-  __shared__ F pl[2][TZ][RY][RX];         // planes of the tile with x/y halo
-  __shared__ F fxs[2][TZ][TY][TX + 1];    // x faces: lower face of each cell, then the last
-  __shared__ F fys[2][TZ][TY + 1][TX];    // y faces
+  // Single buffers suffice: each is rewritten only after a barrier that every
+  // reader of its previous contents has passed (stage | B | slopes | B | faces
+  // | B | divergence | next stage).  The records are read up to the divergence
+  // and rewritten at the next staging, so they alternate.
+  __shared__ F pl[TZ][RY][RX];            // planes of the tile with x/y halo
+  __shared__ F hxs[TZ][TY][TX + 2];       // x half slopes: x0-1, the row, x0+TX
+  __shared__ F hys[TZ][TY + 2][TX];       // y half slopes: y0-1, the rows, y0+TY
+  __shared__ F fxs[TZ][TY][TX + 1];       // x faces: lower face of each cell, then the last
+  __shared__ F fys[TZ][TY + 1][TX];       // y faces
   __shared__ F grec[CURVED ? 2 : 1][CURVED ? NREC * 4 : 1];
 
   // ---- tile (XCD-aware order)
@@ -458,6 +464,21 @@ k_stage(StageArgs a, StagePtrs p) {
   };
   prefetch(0);
 
+  // a thread with no zero-incoming ghost among its slots skips the checks
+  bool anyghost = false;
+  if (CURVED) {
+#pragma unroll
+    for (int j = 0; j < NW; ++j) anyghost |= wzoff[j] >= 0;
+#pragma unroll
+    for (int k = 0; k < TZ; ++k) anyghost |= yzoff[k] >= 0;
+    anyghost |= xh && xzoff >= 0;
+  } else {
+    anyghost = wflag != 0ull || yflag != 0u || (xh && xflag != 0u);
+  }
+  // flat at rest: the direction component is taken out of the face fluxes and
+  // applied once per cell in the divergence
+  constexpr bool NUOUT = !CURVED && !MOVING;
+
   for (int s = 0; s < ns; ++s) {
     const int buf = s & 1;
     // direction components along i1 (z), i2 (y), i3 (x)
@@ -473,23 +494,25 @@ k_stage(StageArgs a, StagePtrs p) {
     // 1. column window in registers, own planes and halos to LDS
     F w[NW];
 #pragma unroll
-    for (int j = 0; j < NW; ++j) {
-      w[j] = wA[j] * (F)pw[j] + wB[j];
-      if (ghost_zero((unsigned)(wflag >> (6 * j)) & 63u, CURVED ? wzoff[j] : -1)) w[j] = F(0);
+    for (int j = 0; j < NW; ++j) w[j] = wA[j] * (F)pw[j] + wB[j];
+    F yv[TZ];
+#pragma unroll
+    for (int k = 0; k < TZ; ++k) yv[k] = yA[k] * (F)py[k] + yB[k];
+    F xv = xA * (F)px + xB;
+    if (anyghost) {
+#pragma unroll
+      for (int j = 0; j < NW; ++j)
+        if (ghost_zero((unsigned)(wflag >> (6 * j)) & 63u, CURVED ? wzoff[j] : -1)) w[j] = F(0);
+#pragma unroll
+      for (int k = 0; k < TZ; ++k)
+        if (ghost_zero((yflag >> (6 * k)) & 63u, CURVED ? yzoff[k] : -1)) yv[k] = F(0);
+      if (ghost_zero(xflag, xzoff)) xv = F(0);
     }
 #pragma unroll
-    for (int k = 0; k < TZ; ++k) pl[buf][k][ty + 2][tx + 2] = w[k + 2];
+    for (int k = 0; k < TZ; ++k) pl[k][ty + 2][tx + 2] = w[k + 2];
 #pragma unroll
-    for (int k = 0; k < TZ; ++k) {
-      F v = yA[k] * (F)py[k] + yB[k];
-      if (ghost_zero((yflag >> (6 * k)) & 63u, CURVED ? yzoff[k] : -1)) v = F(0);
-      pl[buf][k][hry][tx + 2] = v;
-    }
-    if (xh) {
-      F v = xA * (F)px + xB;
-      if (ghost_zero(xflag, xzoff)) v = F(0);
-      pl[buf][hk][ty + 2][hrx] = v;
-    }
+    for (int k = 0; k < TZ; ++k) pl[k][hry][tx + 2] = yv[k];
+    if (xh) pl[hk][ty + 2][hrx] = xv;
     F base[TZ], dang[CURVED ? TZ : 1];
 #pragma unroll
     for (int k = 0; k < TZ; ++k) {
@@ -501,21 +524,50 @@ k_stage(StageArgs a, StagePtrs p) {
     __syncthreads();
     if (s + 1 < ns) prefetch(s + 1);
 
-    // 2. face fluxes.  With half slopes hL, hR either side of a face and the
-    // cell values vm1 | v0, the modified flux of Sec. 3.5 is
+    // 2. half slopes, once per cell and axis: own cells (x, y from LDS, z from
+    // the window), plus the cells just outside the tile that its boundary
+    // faces need (x: lanes < 2 TZ, y: two rows shared over the waves)
+    F sz[NW];
+#pragma unroll
+    for (int k = 0; k < TZ; ++k) {
+      const F v = w[k + 2];
+      hxs[k][ty][tx + 1] = half_slope<LIM>(v - pl[k][ty + 2][tx + 1], pl[k][ty + 2][tx + 3] - v);
+      hys[k][ty + 1][tx] = half_slope<LIM>(v - pl[k][ty + 1][tx + 2], pl[k][ty + 3][tx + 2] - v);
+    }
+#pragma unroll
+    for (int j = 1; j <= TZ + 2; ++j) sz[j] = half_slope<LIM>(w[j] - w[j - 1], w[j + 1] - w[j]);
+    if (tx < 2 * TZ) {
+      const int k = tx >> 1, side = tx & 1;
+      const int c0 = side ? TX + 1 : 0;  // region columns of the cell's stencil
+      const F a0 = pl[k][ty + 2][c0], a1 = pl[k][ty + 2][c0 + 1], a2 = pl[k][ty + 2][c0 + 2];
+      hxs[k][ty][side ? TX + 1 : 0] = half_slope<LIM>(a1 - a0, a2 - a1);
+    }
+#pragma unroll
+    for (int q = ty; q < 2 * TZ; q += TY) {
+      const int k = q >> 1, side = q & 1;
+      const int r0 = side ? TY + 1 : 0;  // region rows of the cell's stencil
+      const F a0 = pl[k][r0][tx + 2], a1 = pl[k][r0 + 1][tx + 2], a2 = pl[k][r0 + 2][tx + 2];
+      hys[k][side ? TY + 1 : 0][tx] = half_slope<LIM>(a1 - a0, a2 - a1);
+    }
+    __syncthreads();
+
+    // 3. face fluxes.  With the cell values vm1 | v0 either side of a face and
+    // their half slopes hL, hR, the modified flux of Sec. 3.5 is
     //   nu > 0:  nu (u (vm1 + hL) + v (v0 - hR) + d (vm1 - v0))
     //   nu < 0:  nu (v (vm1 + hL) + u (v0 - hR) - d (vm1 - v0))
     // plus the advection term aL (vm1 + hL) + aR (v0 - hR) for a moving fluid.
     // curved: gP, gN (one of them zero) and gA from the face's record; flat:
     // the sign of the direction component is uniform over a face group, so
-    // each group takes one branch (POS) with weight nu and advection weight 1
-    auto flux = [&](auto pos_tag, const Face& fc, F gP, F gN, F gA, F vm2, F vm1, F v0, F vp1) -> F {
+    // each group takes one branch (POS) with weight nu (1 when it is applied
+    // in the divergence) and advection weight 1
+    auto flux = [&](auto pos_tag, const Face& fc, F gP, F gN, F gA, F vm1, F hL, F v0, F hR) -> F {
       constexpr int POS = decltype(pos_tag)::value;
-      const F hL = half_slope<LIM>(vm1 - vm2, v0 - vm1), hR = half_slope<LIM>(v0 - vm1, vp1 - v0);
       const F L = vm1 + hL, Rr = v0 - hR, D = vm1 - v0;
       F f;
       if (CURVED)
         f = gP * (fc.u * L + fc.v * Rr + fc.d * D) + gN * (fc.v * L + fc.u * Rr - fc.d * D);
+      else if (NUOUT)
+        f = POS ? fc.u * L + fc.v * Rr + fc.d * D : fc.v * L + fc.u * Rr - fc.d * D;
       else if (POS)
         f = gP * (fc.u * L + fc.v * Rr + fc.d * D);
       else
@@ -523,7 +575,6 @@ k_stage(StageArgs a, StagePtrs p) {
       if (MOVING) f += gA * (fc.aL * L + fc.aR * Rr);
       return f;
     };
-    const F (*P)[RY][RX] = pl[buf];
     // weights of a face from its record (curved) or the direction component
     auto weights = [&](int rec, F nu, F& gP, F& gN, F& gA) {
       if (CURVED) {
@@ -544,15 +595,15 @@ k_stage(StageArgs a, StagePtrs p) {
       for (int k = 0; k < TZ; ++k) {
         F gP, gN, gA;
         weights(k * TY + ty, nx, gP, gN, gA);
-        fxs[buf][k][ty][tx] = flux(pos, fcx[k], gP, gN, gA, P[k][ty + 2][tx], P[k][ty + 2][tx + 1],
-                                   w[k + 2], P[k][ty + 2][tx + 3]);
+        fxs[k][ty][tx] = flux(pos, fcx[k], gP, gN, gA, pl[k][ty + 2][tx + 1], hxs[k][ty][tx], w[k + 2],
+                              hxs[k][ty][tx + 1]);
       }
       if (xe) {
         const int k = tx % TZ;
         F gP, gN, gA;
         weights(k * TY + ty, nx, gP, gN, gA);
-        fxs[buf][k][ty][TX] = flux(pos, fcxe, gP, gN, gA, P[k][ty + 2][TX], P[k][ty + 2][TX + 1],
-                                   P[k][ty + 2][TX + 2], P[k][ty + 2][TX + 3]);
+        fxs[k][ty][TX] = flux(pos, fcxe, gP, gN, gA, pl[k][ty + 2][TX + 1], hxs[k][ty][TX],
+                              pl[k][ty + 2][TX + 2], hxs[k][ty][TX + 1]);
       }
     };
     auto yfaces = [&](auto pos) {
@@ -561,15 +612,15 @@ k_stage(StageArgs a, StagePtrs p) {
       for (int k = 0; k < TZ; ++k) {
         F gP, gN, gA;
         weights(NRX + k * (TY + 1) + ty, ny, gP, gN, gA);
-        fys[buf][k][ty][tx] = flux(pos, fcy[k], gP, gN, gA, P[k][ty][tx + 2], P[k][ty + 1][tx + 2],
-                                   w[k + 2], P[k][ty + 3][tx + 2]);
+        fys[k][ty][tx] = flux(pos, fcy[k], gP, gN, gA, pl[k][ty + 1][tx + 2], hys[k][ty][tx], w[k + 2],
+                              hys[k][ty + 1][tx]);
       }
       if (ye) {
         const int k = ty % TZ;
         F gP, gN, gA;
         weights(NRX + k * (TY + 1) + TY, ny, gP, gN, gA);
-        fys[buf][k][TY][tx] = flux(pos, fcye, gP, gN, gA, P[k][TY][tx + 2], P[k][TY + 1][tx + 2],
-                                   P[k][TY + 2][tx + 2], P[k][TY + 3][tx + 2]);
+        fys[k][TY][tx] = flux(pos, fcye, gP, gN, gA, pl[k][TY + 1][tx + 2], hys[k][TY][tx],
+                              pl[k][TY + 2][tx + 2], hys[k][TY + 1][tx]);
       }
     };
     auto zfaces = [&](auto pos) {
@@ -578,7 +629,7 @@ k_stage(StageArgs a, StagePtrs p) {
       for (int f = 0; f <= TZ; ++f) {
         F gP, gN, gA;
         weights(NRX + NRY + f * TY + ty, nz, gP, gN, gA);
-        fz[f] = flux(pos, fcz[f], gP, gN, gA, w[f], w[f + 1], w[f + 2], w[f + 3]);
+        fz[f] = flux(pos, fcz[f], gP, gN, gA, w[f + 1], sz[f + 1], w[f + 2], sz[f + 2]);
       }
     };
     using TPos = std::integral_constant<int, 1>;
@@ -595,12 +646,14 @@ k_stage(StageArgs a, StagePtrs p) {
     }
     __syncthreads();
 
-    // 3. divergence, update, interaction sums
+    // 4. divergence, update, interaction sums
     const double ws = p.w[s];
+    const F cz = NUOUT ? h * nz * idx0 : h * idx0, cy = NUOUT ? h * ny * idx1 : h * idx1,
+            cx = NUOUT ? h * nx * idx2 : h * idx2;
 #pragma unroll
     for (int k = 0; k < TZ; ++k) {
-      const F dx = fxs[buf][k][ty][tx + 1] - fxs[buf][k][ty][tx];
-      const F dy = fys[buf][k][ty + 1][tx] - fys[buf][k][ty][tx];
+      const F dx = fxs[k][ty][tx + 1] - fxs[k][ty][tx];
+      const F dy = fys[k][ty + 1][tx] - fys[k][ty][tx];
       const F dz = fz[k + 1] - fz[k];
       F It;
       if (CURVED) {
@@ -609,7 +662,7 @@ k_stage(StageArgs a, StagePtrs p) {
         const F x = GR[(k * TY + ty) * 4 + 3];
         It = (x != F(0) ? base[k] : F(0)) - h * (x * (dz + dy + dx) + dang[k]);
       } else {
-        It = base[k] - h * (dz * idx0 + dy * idx1 + dx * idx2);
+        It = base[k] - (dz * cz + dy * cy + dx * cx);
       }
       if (valid[k]) Iout[(long long)s * nc + own(k)] = (S)It;
       // ---- interaction sums (FP64)
