@@ -34,10 +34,11 @@ def build_flat(wl, grid=None, limiter=tr.LIM_MC):
         u_hat = geo.u_hat(_t(wl["u"]))
     v = u_hat[1:] / u_hat[0]
     bc = tuple(BC[b] for b in wl["bc"])
+    bc_hi = tuple(BC[b] for b in wl.get("bc_hi") or wl["bc"])
     pb = Problem(geo=geo, rho=rho, u_hat=u_hat, v=v, model=MODEL[wl["model"]],
                  gamma=wl["gamma"], kappa_a=_t(wl.get("kappa_a")), kappa_s=_t(wl.get("kappa_s")),
                  j=_t(wl.get("j")), C_a=wl.get("C_a", 1.0), C_s=wl.get("C_s", 1.0),
-                 bc_lo=bc, bc_hi=bc, limiter=limiter)
+                 bc_lo=bc, bc_hi=bc_hi, limiter=limiter)
     I0 = _t(wl["I0_iso"]).unsqueeze(0).expand((grid.ns,) + shape).clone()
     T0 = _t(wl["T"]).clone()
     return pb, I0, T0

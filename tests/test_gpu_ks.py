@@ -172,3 +172,18 @@ def test_ks_full_size_fp32_sampled():
         assert rel_l2(Jg, Jo) < 1e-5, rel_l2(Jg, Jo)
         assert rel_l2(Ig[:, lo1:hi1, lo2:hi2][:, H:-H, H:-H].double(), o["I"][:, H:-H, H:-H]) < 1e-5
         assert rel_l2(Tg[lo1:hi1, lo2:hi2][inner], o["T"][inner]) < 1e-5
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_ks_generation3(precision):
+    """642 directions: the angular kernel holds fewer phi cells per workgroup
+    (8 in FP64, 16 in FP32) so that all directions fit its LDS; 5 x 8 x 20
+    cells, so a phi row spans several workgroups with a ragged last one."""
+    wl, I0 = _case(n=(5, 8, 20), generation=3, pole_rows=1)
+    _say(f"torus_ks {precision} g3 5x8x20 2 steps")
+    g = gpu_run(wl, 2, precision=precision, I0=I0)
+    o = oracle_run(wl, 2, I0=I0)
+    if precision == "fp64":
+        _check_fp64(g, o, wl)
+    else:
+        _check_fp32(g, o)

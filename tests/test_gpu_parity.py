@@ -277,3 +277,59 @@ def test_argument_errors():
     with pytest.raises(ValueError):
         ctx.step(I.float(), T, 0.1)
     ctx.close()
+
+
+# --------------------------------------------------------------------------
+# limits of the method and degenerate inputs
+# --------------------------------------------------------------------------
+def test_zero_steps_is_identity():
+    wl = W.brems_flat(n=(6, 5, 7), generation=1, seed=9)
+    ctx = gpu_context(wl)
+    I, T = gpu_initial(ctx, wl)
+    I0, T0 = I.clone(), T.clone()
+    R = torch.full((10, ctx.nc), -7.0, dtype=F64, device="cuda")
+    ctx.step(I, T, wl["dt"], 0, R=R)
+    torch.cuda.synchronize()
+    assert torch.equal(I, I0) and torch.equal(T, T0) and bool((R == -7.0).all())
+    ctx.close()
+
+
+@pytest.mark.parametrize("regime", ["vacuum", "opaque", "below_floor"])
+def test_opacity_limits(regime):
+    """Vacuum (tau = 0: pure upwind transport), optically thick cells
+    (tau ~ 1e3 per step: the flux reduces to its diffusion form and the
+    interaction pins I to B) and density below the floor everywhere (no
+    interaction, T unchanged)."""
+    n = (9, 6, 8)
+    wl = W.brems_flat(n=n, generation=2, seed=13)
+    wl["model"] = "kirchhoff_const"
+    if regime == "vacuum":
+        wl["kappa_a"] = np.zeros(n)
+        wl["kappa_s"] = np.zeros(n)
+    elif regime == "opaque":
+        wl["kappa_a"] = np.full(n, 2.0e3)
+        wl["kappa_s"] = np.full(n, 5.0e2)
+        wl["rho"] = np.ones(n)
+    else:
+        wl["kappa_a"] = np.ones(n)
+        wl["kappa_s"] = np.ones(n)
+        wl["rho"] = np.full(n, 1e-4)
+    I0 = W.random_intensity(162, n, 21, 0.2, 1.2)
+    _say(f"opacity limit {regime}")
+    g = gpu_run(wl, 3, I0=I0)
+    o = oracle_run(wl, 3, I0=I0)
+    _check_fp64(g, o)
+    if regime == "below_floor":
+        assert torch.equal(g["T"], torch.as_tensor(wl["T"], dtype=F64))
+
+
+def test_generation3_step():
+    """642 directions (generation 3), ragged 6 x 5 x 7 box, outflow and
+    zero-incoming sides."""
+    wl = W.brems_flat(n=(6, 5, 7), generation=3, seed=17)
+    wl["bc"] = ("outflow", "zero_incoming", "periodic")
+    wl["bc_hi"] = ("zero_incoming", "outflow", "periodic")
+    _say("generation 3 step, 6x5x7")
+    g = gpu_run(wl, 2)
+    o = oracle_run(wl, 2)
+    _check_fp64(g, o)
