@@ -972,6 +972,12 @@ hipError_t launch_tiled(rt_ctx* c, StageArgs a, const StagePtrs& p, bool stage2,
 hipError_t launch_stage(rt_ctx* c, const StageArgs& a, const StagePtrs& p, bool stage2,
                         hipStream_t st) {
   const bool mc = a.limiter == RT_LIM_MC;
+  // the moving-fluid and curved forms carry more per-cell state (the fluid
+  // velocity, advection weights, records): two cells per column keep them in
+  // registers
+  if (c->fp32 && (c->moving || c->curved))
+    return mc ? launch_tiled<float, float, 2, RT_LIM_MC>(c, a, p, stage2, st)
+              : launch_tiled<float, float, 2, RT_LIM_MINMOD>(c, a, p, stage2, st);
   if (c->fp32)
     return mc ? launch_tiled<float, float, 4, RT_LIM_MC>(c, a, p, stage2, st)
               : launch_tiled<float, float, 4, RT_LIM_MINMOD>(c, a, p, stage2, st);
