@@ -77,7 +77,7 @@ enum { RT_OPAC_KIRCHHOFF_CONST = 0, RT_OPAC_BREMS = 1, RT_OPAC_FIXED_EMISSIVITY 
 enum { RT_TETRAD = 0, RT_COORD = 1 };
 
 typedef struct {
-  int n[3];            /* cells per axis (>= 1); at most 2^31 - 1 cells in total */
+  int n[3];            /* cells per axis (>= 1); at most 2^29 - 1 cells in total */
   double xlo[3];       /* logical lower bounds */
   double xhi[3];       /* logical upper bounds (> xlo) */
   int coords;          /* RT_CART or RT_LOGR_THETA_PHI (x1 = ln r, theta in [0, pi]) */

@@ -186,8 +186,8 @@ rt_status rt_init_grid(const rt_grid_desc* d, rt_ctx** out) {
   if (d->limiter != RT_LIM_MC && d->limiter != RT_LIM_MINMOD) return fail(RT_E_ARG, "rt_init_grid: bad limiter");
   if (!(d->abar >= 0.0) || !(d->rho_floor >= 0.0)) return fail(RT_E_ARG, "rt_init_grid: abar, rho_floor >= 0");
   long long nc = (long long)d->n[0] * d->n[1] * d->n[2];
-  // cell indices are 32-bit inside the stage kernels
-  if (nc >= (1ll << 31)) return fail(RT_E_ARG, "rt_init_grid: at most 2^31 - 1 cells");
+  // the stage kernels address one direction's plane with 32-bit byte offsets
+  if (nc >= (1ll << 29)) return fail(RT_E_ARG, "rt_init_grid: at most 2^29 - 1 cells");
 
   rt_ctx* c = nullptr;
   try {

@@ -59,6 +59,29 @@ __device__ __forceinline__ T half_slope(T p, T q) {
   return T(0.5) * med0(p, q);
 }
 
+// One direction's plane of nc cells as a buffer resource: loads and stores
+// take a uniform base and an unsigned 32-bit byte offset per lane, so the
+// direction loop carries no 64-bit address arithmetic.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const void* base, unsigned bytes) {
+  // stride 0, raw dword addressing (the data-format word of the gfx9 family)
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
+}
+template <typename T>
+__device__ __forceinline__ T bload(__amdgpu_buffer_rsrc_t r, unsigned off) {
+  static_assert(sizeof(T) == 4 || sizeof(T) == 8, "dword or dwordx2");
+  if constexpr (sizeof(T) == 4)
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, 0));
+  else
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0));
+}
+template <typename T>
+__device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, unsigned off, T v) {
+  if constexpr (sizeof(T) == 4)
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, (int)off, 0, 0);
+  else
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(__attribute__((ext_vector_type(2))) unsigned, v), r, (int)off, 0, 0);
+}
+
 // fluid-frame opacities of one cell at temperature T (Sec. 3.6.2)
 __device__ __forceinline__ void opac(const StageArgs& a, const double* __restrict__ rho,
                                      const double* __restrict__ T, const double* __restrict__ ka,
@@ -66,7 +89,8 @@ __device__ __forceinline__ void opac(const StageArgs& a, const double* __restric
                                      double& as) {
   double r = rho[c];
   if (a.model == RT_OPAC_BREMS) {
-    aa = a.C_a * r * r * pow(T[c], -3.5);
+    const double t = T[c];
+    aa = a.C_a * r * r / (t * t * t * sqrt(t));  // T^-3.5
     as = a.C_s * r;
   } else {
     aa = ka ? r * ka[c] : 0.0;
@@ -90,17 +114,20 @@ struct FaceC {
 __device__ __forceinline__ void face_coefs(double tau, double& P, double& Q, double& U, double& V,
                                            double& E) {
   E = exp(-tau);
-  double fa, fb;
+  // fa = ga / tau, fb = gb / tau: the weights are ratios of ga and gb
+  double ga, gb, itau;
+  const double t2 = tau * tau;
   if (tau < 1e-4) {
-    double t2 = tau * tau;
-    fa = 1.0 - 0.25 * t2;
-    fb = tau * (1.0 - 0.25 * t2 * t2);
+    ga = 1.0 - 0.25 * t2;
+    gb = tau * (1.0 - 0.25 * t2 * t2);
+    itau = 1.0;
   } else {
-    double t2 = tau * tau;
-    fa = sqrt(-expm1(-t2)) / tau;
-    fb = sqrt(-expm1(-t2 * t2)) / tau;
+    ga = sqrt(-expm1(-t2));
+    gb = sqrt(-expm1(-t2 * t2));
+    itau = 1.0 / tau;
   }
-  double Wu = fa / (fa + fb), Wd = fb / (fa + fb), Dc = fa * fb / (fa + fb);
+  const double r = 1.0 / (ga + gb);
+  double Wu = ga * r, Wd = gb * r, Dc = ga * gb * r * itau;
   P = E * Wu + Dc;
   Q = E * Wd - Dc;
   U = 0.5 * E * Wu;
@@ -192,7 +219,7 @@ __device__ Solve solve_cell(const StageArgs& a, double r, double T0, double aa, 
 // cells and writes the cell's interaction map.
 // ---------------------------------------------------------------------------
 template <typename S, typename F, int TZ, bool STAGE2, bool MOVING, int LIM, bool CURVED>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
 k_stage(StageArgs a, StagePtrs p) {
   constexpr int TY = 4, NT = TX * TY;
   constexpr int RX = TX + 4, RY = TY + 4;
@@ -325,6 +352,27 @@ k_stage(StageArgs a, StagePtrs p) {
 #pragma unroll
   for (int k = 0; k < TZ; ++k) valid[k] = gx < n3 && gy < n2 && z0 + k < n1;
   auto own = [&](int k) -> long long { return wcell[k + 2]; };
+  // byte offsets of the loaded cells within one direction's plane: they fit in
+  // 32 bits (checked on the host), so every access in the direction loop is a
+  // uniform base plus an unsigned offset and needs no 64-bit address arithmetic
+  unsigned woff[NW], yoff[TZ];
+#pragma unroll
+  for (int j = 0; j < NW; ++j) woff[j] = (unsigned)wcell[j] * (unsigned)sizeof(S);
+#pragma unroll
+  for (int k = 0; k < TZ; ++k) yoff[k] = (unsigned)ycell[k] * (unsigned)sizeof(S);
+  const unsigned xoff = (unsigned)xcell * (unsigned)sizeof(S);
+  // At rest the loads and stores go through buffer resources with these
+  // offsets; the moving kernels, which are register bound, index with the cell
+  // numbers (fewer registers live across their loop).
+  const unsigned pbytes = (unsigned)nc * (unsigned)sizeof(S);
+  auto ld = [&](const S* base, unsigned off, int cell) -> S {
+    if constexpr (MOVING) return base[cell];
+    else return bload<S>(plane_rsrc(base, pbytes), off);
+  };
+  auto st = [&](S* base, unsigned off, int cell, S v) {
+    if constexpr (MOVING) base[cell] = v;
+    else bstore<S>(plane_rsrc(base, pbytes), off, v);
+  };
 
   // ---- coefficients of the faces this thread computes (direction independent)
   auto ahat_of = [&](int c) -> double {
@@ -337,9 +385,10 @@ k_stage(StageArgs a, StagePtrs p) {
     F u, v, d;     // E Wu, E Wd, Dc:  P = u + d, Q = v - d
     F aL, aR;      // advection: (1-E) max(vL, 0), (1-E) min(vR, 0)
   };
-  auto make_face = [&](int axis, int z, int y, int x) -> Face {
+  // ahL, ahR: ahat of the cells below and above the face
+  auto make_face = [&](int axis, int z, int y, int x, double ahL, double ahR) -> Face {
     const int dz = axis == 0, dy = axis == 1, dx = axis == 2;
-    const double tau = a.abar * 0.5 * (ahat_of(gcell(z - dz, y - dy, x - dx)) + ahat_of(gcell(z, y, x))) * a.dt;
+    const double tau = a.abar * 0.5 * (ahL + ahR) * a.dt;
     double P, Q, U, V, E;
     face_coefs(tau, P, Q, U, V, E);
     Face fc;
@@ -361,19 +410,39 @@ k_stage(StageArgs a, StagePtrs p) {
     return fc;
   };
   Face fcx[TZ], fcy[TZ], fcz[TZ + 1];
+  if (MOVING) {
+    // (the moving kernels are register bound: no values are kept across faces)
 #pragma unroll
-  for (int k = 0; k < TZ; ++k) {
-    fcx[k] = make_face(2, z0 + k, gy, gx);
-    fcy[k] = make_face(1, z0 + k, gy, gx);
+    for (int f = 0; f <= TZ; ++f) {
+      fcz[f] = make_face(0, z0 + f, gy, gx, ahat_of(gcell(z0 + f - 1, gy, gx)), ahat_of(gcell(z0 + f, gy, gx)));
+      if (f < TZ) {
+        fcx[f] = make_face(2, z0 + f, gy, gx, ahat_of(gcell(z0 + f, gy, gx - 1)), ahat_of(gcell(z0 + f, gy, gx)));
+        fcy[f] = make_face(1, z0 + f, gy, gx, ahat_of(gcell(z0 + f, gy - 1, gx)), ahat_of(gcell(z0 + f, gy, gx)));
+      }
+    }
+  } else {
+    // walk up the column z0-1 .. z0+TZ, evaluating each cell's ahat once
+    double ahp = ahat_of(gcell(z0 - 1, gy, gx));
+#pragma unroll
+    for (int f = 0; f <= TZ; ++f) {
+      const double ahn = ahat_of(gcell(z0 + f, gy, gx));
+      fcz[f] = make_face(0, z0 + f, gy, gx, ahp, ahn);
+      if (f < TZ) {
+        fcx[f] = make_face(2, z0 + f, gy, gx, ahat_of(gcell(z0 + f, gy, gx - 1)), ahn);
+        fcy[f] = make_face(1, z0 + f, gy, gx, ahat_of(gcell(z0 + f, gy - 1, gx)), ahn);
+      }
+      ahp = ahn;
+    }
   }
-#pragma unroll
-  for (int f = 0; f <= TZ; ++f) fcz[f] = make_face(0, z0 + f, gy, gx);
   // extra faces: the x face above the tile's last column on (row ty, plane
   // lane) for lanes < TZ; the y face above its last row on (column tx, plane
   // ty) for waves ty < TZ
   const bool xe = tx < TZ, ye = ty < TZ;
-  const Face fcxe = make_face(2, z0 + (tx % TZ), gy, x0 + TX);
-  const Face fcye = make_face(1, z0 + (ty % TZ), y0 + TY, gx);
+  const int zxe = z0 + (tx % TZ), zye = z0 + (ty % TZ);
+  const Face fcxe = make_face(2, zxe, gy, x0 + TX, ahat_of(gcell(zxe, gy, x0 + TX - 1)),
+                              ahat_of(gcell(zxe, gy, x0 + TX)));
+  const Face fcye = make_face(1, zye, y0 + TY, gx, ahat_of(gcell(zye, y0 + TY - 1, gx)),
+                              ahat_of(gcell(zye, y0 + TY, gx)));
 
   // ---- own-cell data used in the direction loop
   F bA[TZ], bB[TZ];                        // lazy map of the stage-2 base intensity
@@ -446,20 +515,20 @@ k_stage(StageArgs a, StagePtrs p) {
   auto prefetch = [&](int s) {
     const S* Is = Iflux + (long long)s * nc;
 #pragma unroll
-    for (int j = 0; j < NW; ++j) pw[j] = Is[wcell[j]];
+    for (int j = 0; j < NW; ++j) pw[j] = ld(Is, woff[j], wcell[j]);
 #pragma unroll
-    for (int k = 0; k < TZ; ++k) py[k] = Is[ycell[k]];
-    px = Is[xcell];
+    for (int k = 0; k < TZ; ++k) py[k] = ld(Is, yoff[k], ycell[k]);
+    px = ld(Is, xoff, xcell);
     if (STAGE2) {
       const S* Ib = Ibase + (long long)s * nc;
 #pragma unroll
-      for (int k = 0; k < TZ; ++k) pb[k] = Ib[own(k)];
+      for (int k = 0; k < TZ; ++k) pb[k] = ld(Ib, woff[k + 2], wcell[k + 2]);
     }
     if (CURVED) {
       if (gsrc) gpre = gsrc[(long long)s * gstride];
       const S* As = angD + (long long)s * nc;
 #pragma unroll
-      for (int k = 0; k < TZ; ++k) pda[k] = As[own(k)];
+      for (int k = 0; k < TZ; ++k) pda[k] = ld(As, woff[k + 2], wcell[k + 2]);
     }
   };
   prefetch(0);
@@ -664,7 +733,7 @@ k_stage(StageArgs a, StagePtrs p) {
       } else {
         It = base[k] - (dz * cz + dy * cy + dx * cx);
       }
-      if (valid[k]) Iout[(long long)s * nc + own(k)] = (S)It;
+      if (valid[k]) st(Iout + (long long)s * nc, woff[k + 2], wcell[k + 2], (S)It);
       // ---- interaction sums (FP64)
       const double Itd = (double)(S)It;
       if (MOVING) {
