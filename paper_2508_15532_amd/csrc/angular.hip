@@ -14,7 +14,9 @@
 // One workgroup owns a run of up to CW cells along phi at one (r, theta)
 // position and holds all their directions in LDS; the geometry of the run is
 // shared (it does not depend on phi), so the coefficients are read once per
-// workgroup.
+// workgroup.  The neighbour lists of the geodesic grid are padded to KS_DEG
+// entries (zero weights), so the sum over a direction's neighbours is a fixed,
+// fully unrolled one.
 #include <hip/hip_runtime.h>
 
 #include "ctx.hpp"
@@ -23,24 +25,38 @@
 namespace rt {
 namespace {
 
-// D'_s(c) = A_s I_s(c) + sum_k A_(ns+k) I_(o_k)(c) for the incidences k of s,
-// with the per-(r, theta) coefficients A (scaled to the update on the host).
-// CW cells along phi per workgroup; with CW = 64 a wave owns one direction
-// at a time, so the coefficient and incidence reads are wave-uniform.
+// D'_s(c) = A_s0 I_s(c) + sum_j A_sj I_(o_sj)(c) over the KS_DEG padded
+// neighbours o_sj of s, with the per-(r, theta) coefficients A (scaled to the
+// update on the host).  CW cells along phi per workgroup; with CW = 64 a wave
+// owns one direction at a time, so its coefficient row and neighbour list are
+// wave-uniform and come in as a few wide scalar loads, independent of the
+// intensities, so that they overlap the LDS reads of the previous direction.
 template <typename S, int CW>
 __global__ void __launch_bounds__(256)
-k_angular(long long nc, int n3, int ns, int ninc, const S* __restrict__ I, S* __restrict__ D,
-          const S* __restrict__ coef, const int* __restrict__ inc) {
+k_angular(long long nc, int n3, int ns, const S* __restrict__ I, S* __restrict__ D,
+          const S* __restrict__ coef, const int* __restrict__ nbr) {
   extern __shared__ unsigned char smem_raw[];
-  S* col = reinterpret_cast<S*>(smem_raw);  // [ns][CW]
+  // LDS: the run's intensities [ns][CW], its coefficient rows [ns][KS_ROW] and
+  // the neighbour lists [ns][KS_ROW] (16-bit direction numbers)
+  S* col = reinterpret_cast<S*>(smem_raw);
+  S* lco = col + ns * CW;
+  unsigned short* lnb = reinterpret_cast<unsigned short*>(lco + ns * KS_ROW);
   const int chunks = (n3 + CW - 1) / CW;
   const long long row = blockIdx.x / chunks;  // (i1, i2) position
   const int x0 = (int)(blockIdx.x % chunks) * CW;
   const long long cbase = row * n3 + x0;
   const int t = threadIdx.x;
   const int ncol = min(CW, n3 - x0);
-  // batches of 16 independent loads per thread keep enough reads in flight
-  constexpr int B = 16;
+  // the coefficient rows and neighbour lists go to LDS first; their reads
+  // overlap those of the intensities
+  const S* A = coef + row * (long long)ns * KS_ROW;
+  for (int k = t; k < ns * KS_ROW; k += 256) {
+    lco[k] = A[k];
+    lnb[k] = (unsigned short)nbr[k];
+  }
+  // one or two batches of independent loads per thread: the whole run is in
+  // flight at once
+  constexpr int B = CW >= 64 ? 48 : 24;
   const int total = ns * CW;
   for (int k0 = t; k0 < total; k0 += B * 256) {
     S v[B];
@@ -61,13 +77,14 @@ k_angular(long long nc, int n3, int ns, int ninc, const S* __restrict__ I, S* __
   constexpr int NGRP = 256 / CW;
   int grp = t / CW;
   if (CW == 64) grp = __builtin_amdgcn_readfirstlane(grp);
-  const S* A = coef + row * (long long)(ns + ninc);
-  const int* off = inc;
-  const int* other = inc + ns + 1;
+  static_assert(KS_DEG + 1 <= KS_ROW, "row layout");
+#pragma unroll 2
   for (int s = grp; s < ns; s += NGRP) {
-    S acc = A[s] * col[s * CW + l];
-    const int k1 = off[s + 1];
-    for (int k = off[s]; k < k1; ++k) acc += A[ns + k] * col[other[k] * CW + l];
+    const S* a = lco + s * KS_ROW;
+    const unsigned short* o = lnb + s * KS_ROW;
+    S acc = a[0] * col[s * CW + l];
+#pragma unroll
+    for (int j = 1; j <= KS_DEG; ++j) acc += a[j] * col[o[j] * CW + l];
     if (l < ncol) D[(long long)s * nc + cbase + l] = acc;
   }
 }
@@ -77,18 +94,18 @@ hipError_t launch_cw(rt_ctx* c, const void* I, hipStream_t st) {
   const long long nrt = (long long)c->n[0] * c->n[1];
   const int cw = c->ks_cw;
   const dim3 grid((unsigned)(nrt * ((c->n[2] + cw - 1) / cw))), block(256);
-  const size_t lds = (size_t)c->ns * cw * sizeof(S);
+  const size_t lds = angular_lds_bytes(c->ns, cw, sizeof(S));
   const S* in = (const S*)I;
   S* out = (S*)c->d_angD;
   const S* A = (const S*)c->d_acoef;
   switch (cw) {
-    case 64: hipLaunchKernelGGL((k_angular<S, 64>), grid, block, lds, st, c->nc, c->n[2], c->ns, c->ks_ninc, in, out, A, c->d_inc); break;
-    case 32: hipLaunchKernelGGL((k_angular<S, 32>), grid, block, lds, st, c->nc, c->n[2], c->ns, c->ks_ninc, in, out, A, c->d_inc); break;
-    case 16: hipLaunchKernelGGL((k_angular<S, 16>), grid, block, lds, st, c->nc, c->n[2], c->ns, c->ks_ninc, in, out, A, c->d_inc); break;
-    case 8: hipLaunchKernelGGL((k_angular<S, 8>), grid, block, lds, st, c->nc, c->n[2], c->ns, c->ks_ninc, in, out, A, c->d_inc); break;
-    case 4: hipLaunchKernelGGL((k_angular<S, 4>), grid, block, lds, st, c->nc, c->n[2], c->ns, c->ks_ninc, in, out, A, c->d_inc); break;
-    case 2: hipLaunchKernelGGL((k_angular<S, 2>), grid, block, lds, st, c->nc, c->n[2], c->ns, c->ks_ninc, in, out, A, c->d_inc); break;
-    default: hipLaunchKernelGGL((k_angular<S, 1>), grid, block, lds, st, c->nc, c->n[2], c->ns, c->ks_ninc, in, out, A, c->d_inc); break;
+    case 64: hipLaunchKernelGGL((k_angular<S, 64>), grid, block, lds, st, c->nc, c->n[2], c->ns, in, out, A, c->d_inc); break;
+    case 32: hipLaunchKernelGGL((k_angular<S, 32>), grid, block, lds, st, c->nc, c->n[2], c->ns, in, out, A, c->d_inc); break;
+    case 16: hipLaunchKernelGGL((k_angular<S, 16>), grid, block, lds, st, c->nc, c->n[2], c->ns, in, out, A, c->d_inc); break;
+    case 8: hipLaunchKernelGGL((k_angular<S, 8>), grid, block, lds, st, c->nc, c->n[2], c->ns, in, out, A, c->d_inc); break;
+    case 4: hipLaunchKernelGGL((k_angular<S, 4>), grid, block, lds, st, c->nc, c->n[2], c->ns, in, out, A, c->d_inc); break;
+    case 2: hipLaunchKernelGGL((k_angular<S, 2>), grid, block, lds, st, c->nc, c->n[2], c->ns, in, out, A, c->d_inc); break;
+    default: hipLaunchKernelGGL((k_angular<S, 1>), grid, block, lds, st, c->nc, c->n[2], c->ns, in, out, A, c->d_inc); break;
   }
   return hipGetLastError();
 }

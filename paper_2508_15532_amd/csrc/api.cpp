@@ -128,19 +128,42 @@ rt_status set_kerr_schild(rt_ctx* c, double M, double a, double cfl) {
   } catch (const std::exception& e) {
     return fail(RT_E_ARG, std::string("rt_set_metric: ") + e.what());
   }
-  // angular kernel: the largest run of phi cells whose directions fit 64 KiB of LDS
-  int cw = 64;
-  while (cw > 1 && (size_t)c->ns * cw * c->elem > 65536) cw /= 2;
-  if ((size_t)c->ns * cw * c->elem > 65536)
-    return fail(RT_E_ARG, "rt_set_metric: too many directions for the curved FP64 form");
+  // angular kernel: runs of up to 32 phi cells, as long as the run's LDS stays
+  // within 40 KiB (four workgroups per compute unit); at least one cell within 64 KiB
+  int cw = 32;
+  while (cw > 1 && angular_lds_bytes(c->ns, cw, c->elem) > 40960) cw /= 2;
+  if (angular_lds_bytes(c->ns, cw, c->elem) > 65536)
+    return fail(RT_E_ARG, "rt_set_metric: too many directions for the curved form");
   c->ks_cw = cw;
   c->ks_ninc = T.inc_off[c->ns];
   c->ks_zin_stride = T.zin_stride;
-  std::vector<int> inc(T.inc_off.begin(), T.inc_off.end());
-  inc.insert(inc.end(), T.inc_other.begin(), T.inc_other.end());
+  // angular coefficients padded to a fixed width per direction: slot 0 the
+  // direction itself, slots 1..KS_DEG its neighbours (zero weight and the
+  // direction itself where it has fewer), the rest zero
+  const int ns = c->ns;
+  const size_t nrt = (size_t)c->n[0] * c->n[1];
+  std::vector<int> inc((size_t)ns * KS_ROW, 0);
+  std::vector<double> coef8;
+  try {
+    coef8.assign(nrt * ns * KS_ROW, 0.0);
+  } catch (const std::bad_alloc&) {
+    return fail(RT_E_NOMEM, "rt_set_metric: host allocation failed");
+  }
+  for (int s = 0; s < ns; ++s) {
+    const int k0 = T.inc_off[s], deg = T.inc_off[s + 1] - k0;
+    if (deg > KS_DEG) return fail(RT_E_ARG, "rt_set_metric: a direction has more than 6 neighbours");
+    for (int j = 0; j < KS_ROW; ++j) inc[(size_t)s * KS_ROW + j] = s;
+    for (int j = 0; j < deg; ++j) inc[(size_t)s * KS_ROW + 1 + j] = T.inc_other[k0 + j];
+    for (size_t q = 0; q < nrt; ++q) {
+      const double* A = &T.acoef[q * (ns + c->ks_ninc)];
+      double* D = &coef8[(q * ns + s) * KS_ROW];
+      D[0] = A[s];
+      for (int j = 0; j < deg; ++j) D[1 + j] = A[ns + k0 + j];
+    }
+  }
   rt_status st = RT_OK;
   if ((st = upload_as(c, &c->d_rec_r, T.fr)) || (st = upload_as(c, &c->d_rec_t, T.ft)) ||
-      (st = upload_as(c, &c->d_rec_p, T.fp)) || (st = upload_as(c, &c->d_acoef, T.acoef)) ||
+      (st = upload_as(c, &c->d_rec_p, T.fp)) || (st = upload_as(c, &c->d_acoef, coef8)) ||
       (st = upload(&c->d_zin, T.zin)) ||
       (st = upload(&c->d_nu0, T.nu0)) || (st = upload(&c->d_e, T.e)) ||
       (st = upload(&c->d_einv, T.einv)) || (st = upload(&c->d_inc, inc)) ||

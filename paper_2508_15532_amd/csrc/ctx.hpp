@@ -31,11 +31,11 @@ struct rt_ctx {
   void* d_rec_t = nullptr;       // [ns][N1 (N2+1)][4]
   void* d_rec_p = nullptr;       // [ns][N1 N2][4]
   unsigned char* d_zin = nullptr;
-  void* d_acoef = nullptr;       // [N1 N2][ns + ninc] angular coefficients, transport type
+  void* d_acoef = nullptr;       // [N1 N2][ns][KS_ROW] angular coefficients, transport type
   double* d_nu0 = nullptr;       // [N1 N2]
   double* d_e = nullptr;         // [N1 N2][16] e^mu_a
   double* d_einv = nullptr;      // [N1 N2][16] e^a_mu
-  int* d_inc = nullptr;          // [ns+1] incidence offsets, then [ninc] other direction
+  int* d_inc = nullptr;          // [ns][KS_ROW] the direction, then its neighbours (padded)
   void* d_angD = nullptr;        // [ns][nc] angular divergence scratch
 
   // device grid tables
@@ -83,6 +83,15 @@ struct rt_ctx {
 };
 
 namespace rt {
+
+// angular coupling of the curved geometry: a direction of the geodesic grid
+// has at most KS_DEG neighbours; its coefficient row holds KS_ROW entries
+constexpr int KS_DEG = 6, KS_ROW = 8;
+// LDS of the angular kernel for a run of cw cells: intensities, coefficient
+// rows and 16-bit neighbour lists
+inline size_t angular_lds_bytes(int ns, int cw, size_t elem) {
+  return (size_t)ns * cw * elem + (size_t)ns * KS_ROW * elem + (size_t)ns * KS_ROW * 2;
+}
 
 void set_error(const std::string& msg);
 

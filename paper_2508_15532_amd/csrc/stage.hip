@@ -738,12 +738,14 @@ k_stage(StageArgs a, StagePtrs p) {
       const double Itd = (double)(S)It;
       if (MOVING) {
         const double nb = u0[k] - (u1[k] * p.dirD[s] + u2[k] * p.dirD[ns + s] + u3[k] * p.dirD[2 * ns + s]);
-        const double nb2 = nb * nb;
-        const double Ib = Itd * nb2 * nb2, dOb = ws / nb2;
-        const double den = nu0k[k] + nb * abh[k];
-        acc[k][0] += Ib * dOb;
-        acc[k][1] += nu0k[k] * Ib * dOb / den;
-        acc[k][2] += nb * a.h / (4.0 * kPi * den) * dOb;
+        // with Ib = I~ nb^4, dOb = w / nb^2 and den = n^0 + nb abar h:
+        //   Ib dOb = w I~ nb^2,  n^0 Ib dOb / den,  nb h dOb / (4 pi den) = h w / (4 pi nb den)
+        // (one division: q = 1 / (nb den))
+        const double wI = ws * Itd * (nb * nb);
+        const double q = 1.0 / (nb * (nu0k[k] + nb * abh[k]));
+        acc[k][0] += wI;
+        acc[k][1] += nu0k[k] * wI * nb * q;
+        acc[k][2] += a.h / (4.0 * kPi) * ws * q;
       } else {
         acc[k][0] += ws * Itd;
       }
@@ -847,33 +849,44 @@ k_materialize(long long nc, int ns, double h, const double* __restrict__ map, S*
   const bool use = code == 1.0, zero = code == 2.0;
   const double n0c = nu0 ? nu0[c / n3] : 1.0;
   const double u0 = uhat[c], u1 = uhat[nc + c], u2 = uhat[2 * nc + c], u3 = uhat[3 * nc + c];
+  const double hQ = h / (4.0 * kPi) * Q;
   double R[10];
   for (int m = 0; m < 10; ++m) R[m] = 0.0;
   double g[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int s = 0; s < ns; ++s) {
-    S* q = I + (long long)s * nc + c;
-    const double It = (double)*q;
-    double Io = It;
-    if (use) {
-      double nb = u0 - (u1 * dirD[s] + u2 * dirD[ns + s] + u3 * dirD[2 * ns + s]);
-      double nb2 = nb * nb, nb4 = nb2 * nb2;
-      double den = n0c + nb * ab * h;
-      double cs = n0c / den, ds = nb * h / (4.0 * kPi * den);
-      Io = (cs * It * nb4 + ds * Q) / nb4;
-      *q = (S)Io;
-    } else if (zero) {
-      Io = 0.0;
-      *q = (S)0;
-    }
-    const double Iq = (double)(S)Io;
-    if (Rout)
-      for (int m = 0; m < 10; ++m) R[m] += W16[s * 16 + m] * Iq;
-    if (Gout) {
-      const double dI = w[s] * (Iq - It);
-      g[0] += dI;
-      g[1] += dI * dirD[s];
-      g[2] += dI * dirD[ns + s];
-      g[3] += dI * dirD[2 * ns + s];
+  // batches of B directions: all loads of a batch are issued before its stores
+  constexpr int B = 8;
+  for (int s0 = 0; s0 < ns; s0 += B) {
+    S v[B];
+#pragma unroll
+    for (int u = 0; u < B; ++u) v[u] = I[(long long)min(s0 + u, ns - 1) * nc + c];
+#pragma unroll
+    for (int u = 0; u < B; ++u) {
+      const int s = s0 + u;
+      if (s >= ns) break;
+      S* q = I + (long long)s * nc + c;
+      const double It = (double)v[u];
+      double Io = It;
+      if (use) {
+        // (c_s I~ nb^4 + d_s Q) / nb^4 with c_s = n^0 / den, d_s = nb h / (4 pi den),
+        // den = n^0 + nb abar h, as one division
+        const double nb = u0 - (u1 * dirD[s] + u2 * dirD[ns + s] + u3 * dirD[2 * ns + s]);
+        const double nb3 = nb * nb * nb;
+        Io = (n0c * nb3 * It + hQ) / ((n0c + nb * ab * h) * nb3);
+        *q = (S)Io;
+      } else if (zero) {
+        Io = 0.0;
+        *q = (S)0;
+      }
+      const double Iq = (double)(S)Io;
+      if (Rout)
+        for (int m = 0; m < 10; ++m) R[m] += W16[s * 16 + m] * Iq;
+      if (Gout) {
+        const double dI = w[s] * (Iq - It);
+        g[0] += dI;
+        g[1] += dI * dirD[s];
+        g[2] += dI * dirD[ns + s];
+        g[3] += dI * dirD[2 * ns + s];
+      }
     }
   }
   if (Rout)
@@ -1017,7 +1030,8 @@ hipError_t launch_ordered(rt_ctx* c, Kern kern, StageArgs a, StagePtrs p, int TY
   return hipGetLastError();
 }
 
-template <typename S, typename F, int TZ, int LIM>
+// MOVE: the moving-fluid family (moving fluid or curved geometry), else at rest
+template <typename S, typename F, int TZ, int LIM, bool MOVE>
 hipError_t launch_tiled(rt_ctx* c, StageArgs a, const StagePtrs& p, bool stage2, hipStream_t st) {
   constexpr int TY = 4;
   a.tiles_x = (c->n[2] + TX - 1) / TX;
@@ -1025,16 +1039,18 @@ hipError_t launch_tiled(rt_ctx* c, StageArgs a, const StagePtrs& p, bool stage2,
   a.tiles_z = (c->n[0] + TZ - 1) / TZ;
   a.ntiles = a.tiles_x * a.tiles_y * a.tiles_z;
   a.tiles_per_xcd = (a.ntiles + 7) / 8;
-  if (c->curved) {
-    // curved geometry always runs the moving-fluid form (direction-dependent map)
-    return stage2 ? launch_ordered(c, k_stage<S, F, TZ, true, true, LIM, true>, a, p, TY, TZ, st)
-                  : launch_ordered(c, k_stage<S, F, TZ, false, true, LIM, true>, a, p, TY, TZ, st);
-  }
-  if (c->moving)
+  if constexpr (MOVE) {
+    if (c->curved) {
+      // curved geometry always runs the moving-fluid form (direction-dependent map)
+      return stage2 ? launch_ordered(c, k_stage<S, F, TZ, true, true, LIM, true>, a, p, TY, TZ, st)
+                    : launch_ordered(c, k_stage<S, F, TZ, false, true, LIM, true>, a, p, TY, TZ, st);
+    }
     return stage2 ? launch_ordered(c, k_stage<S, F, TZ, true, true, LIM, false>, a, p, TY, TZ, st)
                   : launch_ordered(c, k_stage<S, F, TZ, false, true, LIM, false>, a, p, TY, TZ, st);
-  return stage2 ? launch_ordered(c, k_stage<S, F, TZ, true, false, LIM, false>, a, p, TY, TZ, st)
-                : launch_ordered(c, k_stage<S, F, TZ, false, false, LIM, false>, a, p, TY, TZ, st);
+  } else {
+    return stage2 ? launch_ordered(c, k_stage<S, F, TZ, true, false, LIM, false>, a, p, TY, TZ, st)
+                  : launch_ordered(c, k_stage<S, F, TZ, false, false, LIM, false>, a, p, TY, TZ, st);
+  }
 }
 }  // namespace
 
@@ -1044,14 +1060,18 @@ hipError_t launch_stage(rt_ctx* c, const StageArgs& a, const StagePtrs& p, bool 
   // the moving-fluid and curved forms carry more per-cell state (the fluid
   // velocity, advection weights, records): two cells per column keep them in
   // registers
-  if (c->fp32 && (c->moving || c->curved))
-    return mc ? launch_tiled<float, float, 2, RT_LIM_MC>(c, a, p, stage2, st)
-              : launch_tiled<float, float, 2, RT_LIM_MINMOD>(c, a, p, stage2, st);
+  const bool mv = c->moving || c->curved;
+  if (c->fp32 && mv)
+    return mc ? launch_tiled<float, float, 2, RT_LIM_MC, true>(c, a, p, stage2, st)
+              : launch_tiled<float, float, 2, RT_LIM_MINMOD, true>(c, a, p, stage2, st);
   if (c->fp32)
-    return mc ? launch_tiled<float, float, 4, RT_LIM_MC>(c, a, p, stage2, st)
-              : launch_tiled<float, float, 4, RT_LIM_MINMOD>(c, a, p, stage2, st);
-  return mc ? launch_tiled<double, double, 2, RT_LIM_MC>(c, a, p, stage2, st)
-            : launch_tiled<double, double, 2, RT_LIM_MINMOD>(c, a, p, stage2, st);
+    return mc ? launch_tiled<float, float, 4, RT_LIM_MC, false>(c, a, p, stage2, st)
+              : launch_tiled<float, float, 4, RT_LIM_MINMOD, false>(c, a, p, stage2, st);
+  if (mv)
+    return mc ? launch_tiled<double, double, 2, RT_LIM_MC, true>(c, a, p, stage2, st)
+              : launch_tiled<double, double, 2, RT_LIM_MINMOD, true>(c, a, p, stage2, st);
+  return mc ? launch_tiled<double, double, 2, RT_LIM_MC, false>(c, a, p, stage2, st)
+            : launch_tiled<double, double, 2, RT_LIM_MINMOD, false>(c, a, p, stage2, st);
 }
 
 hipError_t launch_materialize(rt_ctx* c, void* I, const double* map, double h, double* R,
