@@ -205,16 +205,17 @@ __device__ Solve solve_cell(const StageArgs& a, double r, double T0, double aa, 
 //   1. the thread's column with a two-cell halo along z lives in registers
 //      (the z stencil needs no data movement); the TZ planes of the tile with
 //      a two-cell halo in x and y are staged in LDS (lazy map applied,
-//      zero-incoming ghosts zeroed);
-//   2. every thread computes the face fluxes below its cells along x and y
-//      (stencils from LDS) and all TZ + 1 z faces of its column (registers);
-//      the x faces above the tile's last column and the y faces above its last
-//      row are shared out over otherwise idle lanes; x and y fluxes go to LDS;
-//   3. each thread forms the divergence of its cells (upper x and y faces are
-//      the neighbours' lower faces), writes I~ and adds the cell's FP64
-//      interaction sums.
-// LDS buffers alternate between directions, so two barriers per direction
-// suffice; the next direction's intensities are loaded during steps 2-3.
+//      zero-incoming ghosts zeroed); the next direction's loads are issued;
+//   2. flat at rest: every thread forms the half slopes of its cells and of
+//      their neighbours and both faces of each cell along every axis, from the
+//      planes (x, y) and its column (z), with no further exchange; the planes
+//      alternate between two buffers, so one barrier per direction suffices.
+//      Moving fluid and curved geometry: the half slopes (once per cell and
+//      axis) and then the lower faces go through LDS, with a barrier after
+//      each; the faces above the tile's last column and row are shared out
+//      over otherwise idle lanes;
+//   3. each thread forms the divergence of its cells, writes I~ and adds the
+//      cell's FP64 interaction sums.
 // After the last direction each thread solves the temperature equation of its
 // cells and writes the cell's interaction map.
 // ---------------------------------------------------------------------------
@@ -231,15 +232,20 @@ k_stage(StageArgs a, StagePtrs p) {
   constexpr int NRX = TZ * TY, NRY = TZ * (TY + 1), NRZ = (TZ + 1) * TY;
   constexpr int NREC = NRX + NRY + NRZ;
   static_assert(!CURVED || NREC * 4 <= NT, "one record word per thread");
-  // Single buffers suffice: each is rewritten only after a barrier that every
-  // reader of its previous contents has passed (stage | B | slopes | B | faces
-  // | B | divergence | next stage).  The records are read up to the divergence
-  // and rewritten at the next staging, so they alternate.
-  __shared__ F pl[TZ][RY][RX];            // planes of the tile with x/y halo
-  __shared__ F hxs[TZ][TY][TX + 2];       // x half slopes: x0-1, the row, x0+TX
-  __shared__ F hys[TZ][TY + 2][TX];       // y half slopes: y0-1, the rows, y0+TY
-  __shared__ F fxs[TZ][TY][TX + 1];       // x faces: lower face of each cell, then the last
-  __shared__ F fys[TZ][TY + 1][TX];       // y faces
+  // Unfused, single buffers suffice: each is rewritten only after a barrier
+  // that every reader of its previous contents has passed (stage | B | slopes |
+  // B | faces | B | divergence | next stage).  The records are read up to the
+  // divergence and rewritten at the next staging, so they alternate.
+  // Flat at rest (FUSED) every thread evaluates the slopes and both faces of
+  // its cells itself, so the planes are the only shared data: they alternate
+  // between two buffers and one barrier per direction suffices.
+  constexpr bool FUSED = !CURVED && !MOVING;
+  constexpr int NS = FUSED ? 1 : TZ;     // the slope and face buffers are not used when fused
+  __shared__ F plb[FUSED ? 2 : 1][TZ][RY][RX];  // planes of the tile with x/y halo
+  __shared__ F hxs[NS][TY][TX + 2];       // x half slopes: x0-1, the row, x0+TX
+  __shared__ F hys[NS][TY + 2][TX];       // y half slopes: y0-1, the rows, y0+TY
+  __shared__ F fxs[NS][TY][TX + 1];       // x faces: lower face of each cell, then the last
+  __shared__ F fys[NS][TY + 1][TX];       // y faces
   __shared__ F grec[CURVED ? 2 : 1][CURVED ? NREC * 4 : 1];
 
   // ---- tile (XCD-aware order)
@@ -409,7 +415,7 @@ k_stage(StageArgs a, StagePtrs p) {
     }
     return fc;
   };
-  Face fcx[TZ], fcy[TZ], fcz[TZ + 1];
+  Face fcx[TZ], fcy[TZ], fcz[TZ + 1], fcxu[FUSED ? TZ : 1], fcyu[FUSED ? TZ : 1];
   if (MOVING) {
     // (the moving kernels are register bound: no values are kept across faces)
 #pragma unroll
@@ -430,6 +436,11 @@ k_stage(StageArgs a, StagePtrs p) {
       if (f < TZ) {
         fcx[f] = make_face(2, z0 + f, gy, gx, ahat_of(gcell(z0 + f, gy, gx - 1)), ahn);
         fcy[f] = make_face(1, z0 + f, gy, gx, ahat_of(gcell(z0 + f, gy - 1, gx)), ahn);
+        if (FUSED) {
+          // the upper faces: the same operands as the neighbours' lower faces
+          fcxu[f] = make_face(2, z0 + f, gy, gx + 1, ahn, ahat_of(gcell(z0 + f, gy, gx + 1)));
+          fcyu[f] = make_face(1, z0 + f, gy + 1, gx, ahn, ahat_of(gcell(z0 + f, gy + 1, gx)));
+        }
       }
       ahp = ahn;
     }
@@ -550,6 +561,7 @@ k_stage(StageArgs a, StagePtrs p) {
 
   for (int s = 0; s < ns; ++s) {
     const int buf = s & 1;
+    auto& pl = plb[FUSED ? buf : 0];
     // direction components along i1 (z), i2 (y), i3 (x)
     const F nz = dirF[s], ny = dirF[ns + s], nx = dirF[2 * ns + s];
     // flat zero-incoming: the outside sides that receive zero for this direction
@@ -593,127 +605,175 @@ k_stage(StageArgs a, StagePtrs p) {
     __syncthreads();
     if (s + 1 < ns) prefetch(s + 1);
 
-    // 2. half slopes, once per cell and axis: own cells (x, y from LDS, z from
-    // the window), plus the cells just outside the tile that its boundary
-    // faces need (x: lanes < 2 TZ, y: two rows shared over the waves)
-    F sz[NW];
-#pragma unroll
-    for (int k = 0; k < TZ; ++k) {
-      const F v = w[k + 2];
-      hxs[k][ty][tx + 1] = half_slope<LIM>(v - pl[k][ty + 2][tx + 1], pl[k][ty + 2][tx + 3] - v);
-      hys[k][ty + 1][tx] = half_slope<LIM>(v - pl[k][ty + 1][tx + 2], pl[k][ty + 3][tx + 2] - v);
-    }
-#pragma unroll
-    for (int j = 1; j <= TZ + 2; ++j) sz[j] = half_slope<LIM>(w[j] - w[j - 1], w[j + 1] - w[j]);
-    if (tx < 2 * TZ) {
-      const int k = tx >> 1, side = tx & 1;
-      const int c0 = side ? TX + 1 : 0;  // region columns of the cell's stencil
-      const F a0 = pl[k][ty + 2][c0], a1 = pl[k][ty + 2][c0 + 1], a2 = pl[k][ty + 2][c0 + 2];
-      hxs[k][ty][side ? TX + 1 : 0] = half_slope<LIM>(a1 - a0, a2 - a1);
-    }
-#pragma unroll
-    for (int q = ty; q < 2 * TZ; q += TY) {
-      const int k = q >> 1, side = q & 1;
-      const int r0 = side ? TY + 1 : 0;  // region rows of the cell's stencil
-      const F a0 = pl[k][r0][tx + 2], a1 = pl[k][r0 + 1][tx + 2], a2 = pl[k][r0 + 2][tx + 2];
-      hys[k][side ? TY + 1 : 0][tx] = half_slope<LIM>(a1 - a0, a2 - a1);
-    }
-    __syncthreads();
+    F ddx[TZ], ddy[TZ];  // differences of the x and y face fluxes of the own cells
+    F fz[TZ + 1];        // z faces of the column
+    if constexpr (!FUSED) {
+      // 2. half slopes, once per cell and axis: own cells (x, y from LDS, z from
+      // the window), plus the cells just outside the tile that its boundary
+      // faces need (x: lanes < 2 TZ, y: two rows shared over the waves)
+      F sz[NW];
+  #pragma unroll
+      for (int k = 0; k < TZ; ++k) {
+        const F v = w[k + 2];
+        hxs[k][ty][tx + 1] = half_slope<LIM>(v - pl[k][ty + 2][tx + 1], pl[k][ty + 2][tx + 3] - v);
+        hys[k][ty + 1][tx] = half_slope<LIM>(v - pl[k][ty + 1][tx + 2], pl[k][ty + 3][tx + 2] - v);
+      }
+  #pragma unroll
+      for (int j = 1; j <= TZ + 2; ++j) sz[j] = half_slope<LIM>(w[j] - w[j - 1], w[j + 1] - w[j]);
+      if (tx < 2 * TZ) {
+        const int k = tx >> 1, side = tx & 1;
+        const int c0 = side ? TX + 1 : 0;  // region columns of the cell's stencil
+        const F a0 = pl[k][ty + 2][c0], a1 = pl[k][ty + 2][c0 + 1], a2 = pl[k][ty + 2][c0 + 2];
+        hxs[k][ty][side ? TX + 1 : 0] = half_slope<LIM>(a1 - a0, a2 - a1);
+      }
+  #pragma unroll
+      for (int q = ty; q < 2 * TZ; q += TY) {
+        const int k = q >> 1, side = q & 1;
+        const int r0 = side ? TY + 1 : 0;  // region rows of the cell's stencil
+        const F a0 = pl[k][r0][tx + 2], a1 = pl[k][r0 + 1][tx + 2], a2 = pl[k][r0 + 2][tx + 2];
+        hys[k][side ? TY + 1 : 0][tx] = half_slope<LIM>(a1 - a0, a2 - a1);
+      }
+      __syncthreads();
 
-    // 3. face fluxes.  With the cell values vm1 | v0 either side of a face and
-    // their half slopes hL, hR, the modified flux of Sec. 3.5 is
-    //   nu > 0:  nu (u (vm1 + hL) + v (v0 - hR) + d (vm1 - v0))
-    //   nu < 0:  nu (v (vm1 + hL) + u (v0 - hR) - d (vm1 - v0))
-    // plus the advection term aL (vm1 + hL) + aR (v0 - hR) for a moving fluid.
-    // curved: gP, gN (one of them zero) and gA from the face's record; flat:
-    // the sign of the direction component is uniform over a face group, so
-    // each group takes one branch (POS) with weight nu (1 when it is applied
-    // in the divergence) and advection weight 1
-    auto flux = [&](auto pos_tag, const Face& fc, F gP, F gN, F gA, F vm1, F hL, F v0, F hR) -> F {
-      constexpr int POS = decltype(pos_tag)::value;
-      const F L = vm1 + hL, Rr = v0 - hR, D = vm1 - v0;
-      F f;
-      if (CURVED)
-        f = gP * (fc.u * L + fc.v * Rr + fc.d * D) + gN * (fc.v * L + fc.u * Rr - fc.d * D);
-      else if (NUOUT)
-        f = POS ? fc.u * L + fc.v * Rr + fc.d * D : fc.v * L + fc.u * Rr - fc.d * D;
-      else if (POS)
-        f = gP * (fc.u * L + fc.v * Rr + fc.d * D);
-      else
-        f = gP * (fc.v * L + fc.u * Rr - fc.d * D);
-      if (MOVING) f += gA * (fc.aL * L + fc.aR * Rr);
-      return f;
-    };
-    // weights of a face from its record (curved) or the direction component
-    auto weights = [&](int rec, F nu, F& gP, F& gN, F& gA) {
+      // 3. face fluxes.  With the cell values vm1 | v0 either side of a face and
+      // their half slopes hL, hR, the modified flux of Sec. 3.5 is
+      //   nu > 0:  nu (u (vm1 + hL) + v (v0 - hR) + d (vm1 - v0))
+      //   nu < 0:  nu (v (vm1 + hL) + u (v0 - hR) - d (vm1 - v0))
+      // plus the advection term aL (vm1 + hL) + aR (v0 - hR) for a moving fluid.
+      // curved: gP, gN (one of them zero) and gA from the face's record; flat:
+      // the sign of the direction component is uniform over a face group, so
+      // each group takes one branch (POS) with weight nu (1 when it is applied
+      // in the divergence) and advection weight 1
+      auto flux = [&](auto pos_tag, const Face& fc, F gP, F gN, F gA, F vm1, F hL, F v0, F hR) -> F {
+        constexpr int POS = decltype(pos_tag)::value;
+        const F L = vm1 + hL, Rr = v0 - hR, D = vm1 - v0;
+        F f;
+        if (CURVED)
+          f = gP * (fc.u * L + fc.v * Rr + fc.d * D) + gN * (fc.v * L + fc.u * Rr - fc.d * D);
+        else if (NUOUT)
+          f = POS ? fc.u * L + fc.v * Rr + fc.d * D : fc.v * L + fc.u * Rr - fc.d * D;
+        else if (POS)
+          f = gP * (fc.u * L + fc.v * Rr + fc.d * D);
+        else
+          f = gP * (fc.v * L + fc.u * Rr - fc.d * D);
+        if (MOVING) f += gA * (fc.aL * L + fc.aR * Rr);
+        return f;
+      };
+      // weights of a face from its record (curved) or the direction component
+      auto weights = [&](int rec, F nu, F& gP, F& gN, F& gA) {
+        if (CURVED) {
+          const F* r = GR + rec * 4;
+          gP = r[0];
+          gN = r[1];
+          gA = r[2];
+        } else {
+          gP = nu;
+          gN = F(0);
+          gA = F(1);
+        }
+      };
+      auto xfaces = [&](auto pos) {
+        // x faces below each own cell; the extra one above the last column
+  #pragma unroll
+        for (int k = 0; k < TZ; ++k) {
+          F gP, gN, gA;
+          weights(k * TY + ty, nx, gP, gN, gA);
+          fxs[k][ty][tx] = flux(pos, fcx[k], gP, gN, gA, pl[k][ty + 2][tx + 1], hxs[k][ty][tx], w[k + 2],
+                                hxs[k][ty][tx + 1]);
+        }
+        if (xe) {
+          const int k = tx % TZ;
+          F gP, gN, gA;
+          weights(k * TY + ty, nx, gP, gN, gA);
+          fxs[k][ty][TX] = flux(pos, fcxe, gP, gN, gA, pl[k][ty + 2][TX + 1], hxs[k][ty][TX],
+                                pl[k][ty + 2][TX + 2], hxs[k][ty][TX + 1]);
+        }
+      };
+      auto yfaces = [&](auto pos) {
+        // y faces below each own cell; the extra one above the last row
+  #pragma unroll
+        for (int k = 0; k < TZ; ++k) {
+          F gP, gN, gA;
+          weights(NRX + k * (TY + 1) + ty, ny, gP, gN, gA);
+          fys[k][ty][tx] = flux(pos, fcy[k], gP, gN, gA, pl[k][ty + 1][tx + 2], hys[k][ty][tx], w[k + 2],
+                                hys[k][ty + 1][tx]);
+        }
+        if (ye) {
+          const int k = ty % TZ;
+          F gP, gN, gA;
+          weights(NRX + k * (TY + 1) + TY, ny, gP, gN, gA);
+          fys[k][TY][tx] = flux(pos, fcye, gP, gN, gA, pl[k][TY + 1][tx + 2], hys[k][TY][tx],
+                                pl[k][TY + 2][tx + 2], hys[k][TY + 1][tx]);
+        }
+      };
+      auto zfaces = [&](auto pos) {
+        // z faces of the column, from registers
+  #pragma unroll
+        for (int f = 0; f <= TZ; ++f) {
+          F gP, gN, gA;
+          weights(NRX + NRY + f * TY + ty, nz, gP, gN, gA);
+          fz[f] = flux(pos, fcz[f], gP, gN, gA, w[f + 1], sz[f + 1], w[f + 2], sz[f + 2]);
+        }
+      };
+      using TPos = std::integral_constant<int, 1>;
+      using TNeg = std::integral_constant<int, 0>;
       if (CURVED) {
-        const F* r = GR + rec * 4;
-        gP = r[0];
-        gN = r[1];
-        gA = r[2];
+        xfaces(TPos{});
+        yfaces(TPos{});
+        zfaces(TPos{});
       } else {
-        gP = nu;
-        gN = F(0);
-        gA = F(1);
+        auto up = [](F nu) { return __builtin_amdgcn_readfirstlane(nu > F(0) ? 1 : 0) != 0; };
+        if (up(nx)) xfaces(TPos{}); else xfaces(TNeg{});
+        if (up(ny)) yfaces(TPos{}); else yfaces(TNeg{});
+        if (up(nz)) zfaces(TPos{}); else zfaces(TNeg{});
       }
-    };
-    F fz[TZ + 1];
-    auto xfaces = [&](auto pos) {
-      // x faces below each own cell; the extra one above the last column
+      __syncthreads();
 #pragma unroll
       for (int k = 0; k < TZ; ++k) {
-        F gP, gN, gA;
-        weights(k * TY + ty, nx, gP, gN, gA);
-        fxs[k][ty][tx] = flux(pos, fcx[k], gP, gN, gA, pl[k][ty + 2][tx + 1], hxs[k][ty][tx], w[k + 2],
-                              hxs[k][ty][tx + 1]);
+        ddx[k] = fxs[k][ty][tx + 1] - fxs[k][ty][tx];
+        ddy[k] = fys[k][ty + 1][tx] - fys[k][ty][tx];
       }
-      if (xe) {
-        const int k = tx % TZ;
-        F gP, gN, gA;
-        weights(k * TY + ty, nx, gP, gN, gA);
-        fxs[k][ty][TX] = flux(pos, fcxe, gP, gN, gA, pl[k][ty + 2][TX + 1], hxs[k][ty][TX],
-                              pl[k][ty + 2][TX + 2], hxs[k][ty][TX + 1]);
-      }
-    };
-    auto yfaces = [&](auto pos) {
-      // y faces below each own cell; the extra one above the last row
-#pragma unroll
-      for (int k = 0; k < TZ; ++k) {
-        F gP, gN, gA;
-        weights(NRX + k * (TY + 1) + ty, ny, gP, gN, gA);
-        fys[k][ty][tx] = flux(pos, fcy[k], gP, gN, gA, pl[k][ty + 1][tx + 2], hys[k][ty][tx], w[k + 2],
-                              hys[k][ty + 1][tx]);
-      }
-      if (ye) {
-        const int k = ty % TZ;
-        F gP, gN, gA;
-        weights(NRX + k * (TY + 1) + TY, ny, gP, gN, gA);
-        fys[k][TY][tx] = flux(pos, fcye, gP, gN, gA, pl[k][TY + 1][tx + 2], hys[k][TY][tx],
-                              pl[k][TY + 2][tx + 2], hys[k][TY + 1][tx]);
-      }
-    };
-    auto zfaces = [&](auto pos) {
-      // z faces of the column, from registers
-#pragma unroll
-      for (int f = 0; f <= TZ; ++f) {
-        F gP, gN, gA;
-        weights(NRX + NRY + f * TY + ty, nz, gP, gN, gA);
-        fz[f] = flux(pos, fcz[f], gP, gN, gA, w[f + 1], sz[f + 1], w[f + 2], sz[f + 2]);
-      }
-    };
-    using TPos = std::integral_constant<int, 1>;
-    using TNeg = std::integral_constant<int, 0>;
-    if (CURVED) {
-      xfaces(TPos{});
-      yfaces(TPos{});
-      zfaces(TPos{});
     } else {
+      // 2'. slopes and both faces of the own cells along every axis: x and y
+      // from the staged planes, z from the column window.  A face shared by
+      // two cells is evaluated by both threads from the same operands.
+      auto fpos = [&](auto pos_tag, const Face& fc, F vm1, F hL, F v0, F hR) -> F {
+        constexpr int POS = decltype(pos_tag)::value;
+        const F L = vm1 + hL, Rr = v0 - hR, D = vm1 - v0;
+        return POS ? fc.u * L + fc.v * Rr + fc.d * D : fc.v * L + fc.u * Rr - fc.d * D;
+      };
+      // upper minus lower face flux of the cell c2 from the values c0 .. c4 along the axis
+      auto div1 = [&](auto pos, const Face& lo, const Face& hi, F c0, F c1, F c2, F c3, F c4) -> F {
+        const F hm = half_slope<LIM>(c1 - c0, c2 - c1), h0 = half_slope<LIM>(c2 - c1, c3 - c2),
+                hp = half_slope<LIM>(c3 - c2, c4 - c3);
+        return fpos(pos, hi, c2, h0, c3, hp) - fpos(pos, lo, c1, hm, c2, h0);
+      };
+      auto xpart = [&](auto pos) {
+#pragma unroll
+        for (int k = 0; k < TZ; ++k)
+          ddx[k] = div1(pos, fcx[k], fcxu[k], pl[k][ty + 2][tx], pl[k][ty + 2][tx + 1], w[k + 2],
+                        pl[k][ty + 2][tx + 3], pl[k][ty + 2][tx + 4]);
+      };
+      auto ypart = [&](auto pos) {
+#pragma unroll
+        for (int k = 0; k < TZ; ++k)
+          ddy[k] = div1(pos, fcy[k], fcyu[k], pl[k][ty][tx + 2], pl[k][ty + 1][tx + 2], w[k + 2],
+                        pl[k][ty + 3][tx + 2], pl[k][ty + 4][tx + 2]);
+      };
+      auto zpart = [&](auto pos) {
+        F sz[NW];
+#pragma unroll
+        for (int j = 1; j <= TZ + 2; ++j) sz[j] = half_slope<LIM>(w[j] - w[j - 1], w[j + 1] - w[j]);
+#pragma unroll
+        for (int f = 0; f <= TZ; ++f) fz[f] = fpos(pos, fcz[f], w[f + 1], sz[f + 1], w[f + 2], sz[f + 2]);
+      };
+      using TPos = std::integral_constant<int, 1>;
+      using TNeg = std::integral_constant<int, 0>;
       auto up = [](F nu) { return __builtin_amdgcn_readfirstlane(nu > F(0) ? 1 : 0) != 0; };
-      if (up(nx)) xfaces(TPos{}); else xfaces(TNeg{});
-      if (up(ny)) yfaces(TPos{}); else yfaces(TNeg{});
-      if (up(nz)) zfaces(TPos{}); else zfaces(TNeg{});
+      if (up(nx)) xpart(TPos{}); else xpart(TNeg{});
+      if (up(ny)) ypart(TPos{}); else ypart(TNeg{});
+      if (up(nz)) zpart(TPos{}); else zpart(TNeg{});
     }
-    __syncthreads();
 
     // 4. divergence, update, interaction sums
     const double ws = p.w[s];
@@ -721,8 +781,7 @@ k_stage(StageArgs a, StagePtrs p) {
             cx = NUOUT ? h * nx * idx2 : h * idx2;
 #pragma unroll
     for (int k = 0; k < TZ; ++k) {
-      const F dx = fxs[k][ty][tx + 1] - fxs[k][ty][tx];
-      const F dy = fys[k][ty + 1][tx] - fys[k][ty][tx];
+      const F dx = ddx[k], dy = ddy[k];
       const F dz = fz[k + 1] - fz[k];
       F It;
       if (CURVED) {
