@@ -74,12 +74,15 @@ __device__ __forceinline__ T bload(__amdgpu_buffer_rsrc_t r, unsigned off) {
   else
     return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0));
 }
+// stores are marked non-temporal (cache policy bit 1 on this target): the
+// kernel never reads back what it writes, so these lines go first when L2
+// needs room and the staged planes of the neighbouring tiles stay resident
 template <typename T>
 __device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, unsigned off, T v) {
   if constexpr (sizeof(T) == 4)
-    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, (int)off, 0, 0);
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, (int)off, 0, 2);
   else
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(__attribute__((ext_vector_type(2))) unsigned, v), r, (int)off, 0, 0);
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(__attribute__((ext_vector_type(2))) unsigned, v), r, (int)off, 0, 2);
 }
 
 // fluid-frame opacities of one cell at temperature T (Sec. 3.6.2)
