@@ -209,14 +209,14 @@ __device__ Solve solve_cell(const StageArgs& a, double r, double T0, double aa, 
 //      (the z stencil needs no data movement); the TZ planes of the tile with
 //      a two-cell halo in x and y are staged in LDS (lazy map applied,
 //      zero-incoming ghosts zeroed); the next direction's loads are issued;
-//   2. flat at rest: every thread forms the half slopes of its cells and of
-//      their neighbours and both faces of each cell along every axis, from the
+//   2. every thread forms the half slopes of its cells and of their
+//      neighbours and both faces of each cell along every axis, from the
 //      planes (x, y) and its column (z), with no further exchange; the planes
-//      alternate between two buffers, so one barrier per direction suffices.
-//      Moving fluid and curved geometry: the half slopes (once per cell and
-//      axis) and then the lower faces go through LDS, with a barrier after
-//      each; the faces above the tile's last column and row are shared out
-//      over otherwise idle lanes;
+//      (and the curved face records) alternate between two buffers, so one
+//      barrier per direction suffices.  The FP64 moving-fluid kernels, short
+//      of registers, instead pass the half slopes (once per cell and axis) and
+//      then the lower faces through LDS, with a barrier after each; the faces
+//      above the tile's last column and row are shared out over idle lanes;
 //   3. each thread forms the divergence of its cells, writes I~ and adds the
 //      cell's FP64 interaction sums.
 // After the last direction each thread solves the temperature equation of its
@@ -239,10 +239,12 @@ k_stage(StageArgs a, StagePtrs p) {
   // that every reader of its previous contents has passed (stage | B | slopes |
   // B | faces | B | divergence | next stage).  The records are read up to the
   // divergence and rewritten at the next staging, so they alternate.
-  // Flat at rest (FUSED) every thread evaluates the slopes and both faces of
-  // its cells itself, so the planes are the only shared data: they alternate
-  // between two buffers and one barrier per direction suffices.
-  constexpr bool FUSED = !CURVED && !MOVING;
+  // FUSED: every thread evaluates the slopes and both faces of its cells
+  // itself, so the planes (and the curved records) are the only shared data:
+  // they alternate between two buffers and one barrier per direction suffices.
+  // The FP64 moving-fluid kernels keep the exchange through LDS: the upper
+  // faces' coefficients would not fit their registers.
+  constexpr bool FUSED = sizeof(F) == 4 || !MOVING;
   constexpr int NS = FUSED ? 1 : TZ;     // the slope and face buffers are not used when fused
   __shared__ F plb[FUSED ? 2 : 1][TZ][RY][RX];  // planes of the tile with x/y halo
   __shared__ F hxs[NS][TY][TX + 2];       // x half slopes: x0-1, the row, x0+TX
@@ -427,6 +429,10 @@ k_stage(StageArgs a, StagePtrs p) {
       if (f < TZ) {
         fcx[f] = make_face(2, z0 + f, gy, gx, ahat_of(gcell(z0 + f, gy, gx - 1)), ahat_of(gcell(z0 + f, gy, gx)));
         fcy[f] = make_face(1, z0 + f, gy, gx, ahat_of(gcell(z0 + f, gy - 1, gx)), ahat_of(gcell(z0 + f, gy, gx)));
+        if (FUSED) {
+          fcxu[f] = make_face(2, z0 + f, gy, gx + 1, ahat_of(gcell(z0 + f, gy, gx)), ahat_of(gcell(z0 + f, gy, gx + 1)));
+          fcyu[f] = make_face(1, z0 + f, gy + 1, gx, ahat_of(gcell(z0 + f, gy, gx)), ahat_of(gcell(z0 + f, gy + 1, gx)));
+        }
       }
     }
   } else {
@@ -740,42 +746,62 @@ k_stage(StageArgs a, StagePtrs p) {
       // 2'. slopes and both faces of the own cells along every axis: x and y
       // from the staged planes, z from the column window.  A face shared by
       // two cells is evaluated by both threads from the same operands.
-      auto fpos = [&](auto pos_tag, const Face& fc, F vm1, F hL, F v0, F hR) -> F {
+      // the modified flux of Sec. 3.5 through one face (see the unfused path)
+      auto fpos = [&](auto pos_tag, const Face& fc, int rec, F nu, F vm1, F hL, F v0, F hR) -> F {
         constexpr int POS = decltype(pos_tag)::value;
         const F L = vm1 + hL, Rr = v0 - hR, D = vm1 - v0;
-        return POS ? fc.u * L + fc.v * Rr + fc.d * D : fc.v * L + fc.u * Rr - fc.d * D;
+        F f;
+        if (CURVED) {
+          const F* r = GR + rec * 4;
+          f = r[0] * (fc.u * L + fc.v * Rr + fc.d * D) + r[1] * (fc.v * L + fc.u * Rr - fc.d * D);
+          if (MOVING) f += r[2] * (fc.aL * L + fc.aR * Rr);
+        } else {
+          f = POS ? fc.u * L + fc.v * Rr + fc.d * D : fc.v * L + fc.u * Rr - fc.d * D;
+          if (!NUOUT) f *= nu;
+          if (MOVING) f += fc.aL * L + fc.aR * Rr;
+        }
+        return f;
       };
       // upper minus lower face flux of the cell c2 from the values c0 .. c4 along the axis
-      auto div1 = [&](auto pos, const Face& lo, const Face& hi, F c0, F c1, F c2, F c3, F c4) -> F {
+      auto div1 = [&](auto pos, const Face& lo, const Face& hi, int rlo, int rhi, F nu, F c0, F c1, F c2,
+                      F c3, F c4) -> F {
         const F hm = half_slope<LIM>(c1 - c0, c2 - c1), h0 = half_slope<LIM>(c2 - c1, c3 - c2),
                 hp = half_slope<LIM>(c3 - c2, c4 - c3);
-        return fpos(pos, hi, c2, h0, c3, hp) - fpos(pos, lo, c1, hm, c2, h0);
+        return fpos(pos, hi, rhi, nu, c2, h0, c3, hp) - fpos(pos, lo, rlo, nu, c1, hm, c2, h0);
       };
       auto xpart = [&](auto pos) {
 #pragma unroll
         for (int k = 0; k < TZ; ++k)
-          ddx[k] = div1(pos, fcx[k], fcxu[k], pl[k][ty + 2][tx], pl[k][ty + 2][tx + 1], w[k + 2],
-                        pl[k][ty + 2][tx + 3], pl[k][ty + 2][tx + 4]);
+          ddx[k] = div1(pos, fcx[k], fcxu[k], k * TY + ty, k * TY + ty, nx, pl[k][ty + 2][tx],
+                        pl[k][ty + 2][tx + 1], w[k + 2], pl[k][ty + 2][tx + 3], pl[k][ty + 2][tx + 4]);
       };
       auto ypart = [&](auto pos) {
 #pragma unroll
         for (int k = 0; k < TZ; ++k)
-          ddy[k] = div1(pos, fcy[k], fcyu[k], pl[k][ty][tx + 2], pl[k][ty + 1][tx + 2], w[k + 2],
-                        pl[k][ty + 3][tx + 2], pl[k][ty + 4][tx + 2]);
+          ddy[k] = div1(pos, fcy[k], fcyu[k], NRX + k * (TY + 1) + ty, NRX + k * (TY + 1) + ty + 1, ny,
+                        pl[k][ty][tx + 2], pl[k][ty + 1][tx + 2], w[k + 2], pl[k][ty + 3][tx + 2],
+                        pl[k][ty + 4][tx + 2]);
       };
       auto zpart = [&](auto pos) {
         F sz[NW];
 #pragma unroll
         for (int j = 1; j <= TZ + 2; ++j) sz[j] = half_slope<LIM>(w[j] - w[j - 1], w[j + 1] - w[j]);
 #pragma unroll
-        for (int f = 0; f <= TZ; ++f) fz[f] = fpos(pos, fcz[f], w[f + 1], sz[f + 1], w[f + 2], sz[f + 2]);
+        for (int f = 0; f <= TZ; ++f)
+          fz[f] = fpos(pos, fcz[f], NRX + NRY + f * TY + ty, nz, w[f + 1], sz[f + 1], w[f + 2], sz[f + 2]);
       };
+      if (CURVED) {
+        xpart(std::integral_constant<int, 1>{});
+        ypart(std::integral_constant<int, 1>{});
+        zpart(std::integral_constant<int, 1>{});
+      } else {
       using TPos = std::integral_constant<int, 1>;
       using TNeg = std::integral_constant<int, 0>;
       auto up = [](F nu) { return __builtin_amdgcn_readfirstlane(nu > F(0) ? 1 : 0) != 0; };
       if (up(nx)) xpart(TPos{}); else xpart(TNeg{});
       if (up(ny)) ypart(TPos{}); else ypart(TNeg{});
       if (up(nz)) zpart(TPos{}); else zpart(TNeg{});
+      }
     }
 
     // 4. divergence, update, interaction sums
