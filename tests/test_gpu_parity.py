@@ -101,6 +101,32 @@ def test_variants_fp64(case):
     assert (g["G"] - o["G"]).abs().max().item() < 1e-10 * scale
 
 
+@pytest.mark.parametrize("case", range(len(CASES)))
+def test_variants_fp32(case):
+    # the FP32 kernels at rest and with a moving fluid (advection term) over the
+    # boundary kinds, limiters and models, on two x tiles (the second ragged)
+    model, bc, lim, moving, floor, weights = CASES[case]
+    n = (9, 6, 70)  # two x tiles, a ragged one among them
+    rng = np.random.default_rng(500 + case)
+    wl = W.brems_flat(n=n, generation=1, seed=600 + case)
+    wl.update(model=model, bc=bc, weights=weights,
+              kappa_a=rng.uniform(0.05, 4.0, n), kappa_s=rng.uniform(0.0, 2.0, n),
+              j=rng.uniform(0.0, 1.0, n))
+    if moving:
+        wl["u"] = moving_fluid(n, 700 + case)
+    if floor:
+        rho = wl["rho"].copy()
+        rho[rng.uniform(size=n) < 0.2] = 1e-5
+        wl["rho"] = rho
+    I0 = W.random_intensity(42, n, 800 + case, 0.0, 0.3)
+    _say(f"fp32 variant {case}: {model} {bc} {lim} moving={moving} floor={floor}")
+    g = gpu_run(wl, 3, I0=I0, limiter=lim, want_G=True, precision="fp32")
+    o = oracle_run(wl, 3, I0=I0, limiter={"mc": 0, "minmod": 1}[lim], want_G=True)
+    _check_fp32(g, o)
+    gI = g["I"].double()
+    assert rel_l2(gI, o["I"]) < 1e-5, rel_l2(gI, o["I"])
+
+
 @pytest.mark.parametrize("shape", [(1, 1, 37), (1, 6, 1), (3, 1, 70)])
 def test_degenerate_axes(shape):
     wl = W.brems_flat(n=shape, generation=1, seed=7)
