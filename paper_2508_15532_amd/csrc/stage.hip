@@ -213,10 +213,7 @@ __device__ Solve solve_cell(const StageArgs& a, double r, double T0, double aa, 
 //      neighbours and both faces of each cell along every axis, from the
 //      planes (x, y) and its column (z), with no further exchange; the planes
 //      (and the curved face records) alternate between two buffers, so one
-//      barrier per direction suffices.  The FP64 moving-fluid kernels, short
-//      of registers, instead pass the half slopes (once per cell and axis) and
-//      then the lower faces through LDS, with a barrier after each; the faces
-//      above the tile's last column and row are shared out over idle lanes;
+//      barrier per direction suffices;
 //   3. each thread forms the divergence of its cells, writes I~ and adds the
 //      cell's FP64 interaction sums.
 // After the last direction each thread solves the temperature equation of its
@@ -228,29 +225,19 @@ k_stage(StageArgs a, StagePtrs p) {
   constexpr int TY = 4, NT = TX * TY;
   constexpr int RX = TX + 4, RY = TY + 4;
   constexpr int NW = TZ + 4;  // column window: planes z0-2 .. z0+TZ+1
-  static_assert(TZ <= TY, "the extra y faces are shared out one plane per wave");
+  static_assert(4 * TZ <= TX, "the x halo takes four lanes per plane");
   // curved geometry: per-direction face records {gP, gN, gA, x} for the x
   // (phi) rows (k, ty) -- x holds the centre factor --, the y (theta) faces
   // (k, 0..TY) and the z (r) faces (0..TZ, ty)
   constexpr int NRX = TZ * TY, NRY = TZ * (TY + 1), NRZ = (TZ + 1) * TY;
   constexpr int NREC = NRX + NRY + NRZ;
   static_assert(!CURVED || NREC * 4 <= NT, "one record word per thread");
-  // Unfused, single buffers suffice: each is rewritten only after a barrier
-  // that every reader of its previous contents has passed (stage | B | slopes |
-  // B | faces | B | divergence | next stage).  The records are read up to the
-  // divergence and rewritten at the next staging, so they alternate.
-  // FUSED: every thread evaluates the slopes and both faces of its cells
-  // itself, so the planes (and the curved records) are the only shared data:
-  // they alternate between two buffers and one barrier per direction suffices.
-  // The FP64 moving-fluid kernels keep the exchange through LDS: the upper
-  // faces' coefficients would not fit their registers.
-  constexpr bool FUSED = sizeof(F) == 4 || !MOVING;
-  constexpr int NS = FUSED ? 1 : TZ;     // the slope and face buffers are not used when fused
-  __shared__ F plb[FUSED ? 2 : 1][TZ][RY][RX];  // planes of the tile with x/y halo
-  __shared__ F hxs[NS][TY][TX + 2];       // x half slopes: x0-1, the row, x0+TX
-  __shared__ F hys[NS][TY + 2][TX];       // y half slopes: y0-1, the rows, y0+TY
-  __shared__ F fxs[NS][TY][TX + 1];       // x faces: lower face of each cell, then the last
-  __shared__ F fys[NS][TY + 1][TX];       // y faces
+  // Every thread evaluates the slopes and both faces of its cells itself, so
+  // the planes and the curved records are the only shared data: they
+  // alternate between two buffers (a buffer is rewritten two directions later,
+  // after a barrier that every reader of it has passed), and one barrier per
+  // direction suffices.
+  __shared__ F plb[2][TZ][RY][RX];  // planes of the tile with x/y halo
   __shared__ F grec[CURVED ? 2 : 1][CURVED ? NREC * 4 : 1];
 
   // ---- tile (XCD-aware order)
@@ -420,7 +407,10 @@ k_stage(StageArgs a, StagePtrs p) {
     }
     return fc;
   };
-  Face fcx[TZ], fcy[TZ], fcz[TZ + 1], fcxu[FUSED ? TZ : 1], fcyu[FUSED ? TZ : 1];
+  // lower faces of the own cells along x and y (fcx, fcy), their upper faces
+  // (fcxu, fcyu: the same operands as the neighbours' lower faces), and the
+  // TZ + 1 z faces of the column
+  Face fcx[TZ], fcy[TZ], fcz[TZ + 1], fcxu[TZ], fcyu[TZ];
   if (MOVING) {
     // (the moving kernels are register bound: no values are kept across faces)
 #pragma unroll
@@ -429,10 +419,8 @@ k_stage(StageArgs a, StagePtrs p) {
       if (f < TZ) {
         fcx[f] = make_face(2, z0 + f, gy, gx, ahat_of(gcell(z0 + f, gy, gx - 1)), ahat_of(gcell(z0 + f, gy, gx)));
         fcy[f] = make_face(1, z0 + f, gy, gx, ahat_of(gcell(z0 + f, gy - 1, gx)), ahat_of(gcell(z0 + f, gy, gx)));
-        if (FUSED) {
-          fcxu[f] = make_face(2, z0 + f, gy, gx + 1, ahat_of(gcell(z0 + f, gy, gx)), ahat_of(gcell(z0 + f, gy, gx + 1)));
-          fcyu[f] = make_face(1, z0 + f, gy + 1, gx, ahat_of(gcell(z0 + f, gy, gx)), ahat_of(gcell(z0 + f, gy + 1, gx)));
-        }
+        fcxu[f] = make_face(2, z0 + f, gy, gx + 1, ahat_of(gcell(z0 + f, gy, gx)), ahat_of(gcell(z0 + f, gy, gx + 1)));
+        fcyu[f] = make_face(1, z0 + f, gy + 1, gx, ahat_of(gcell(z0 + f, gy, gx)), ahat_of(gcell(z0 + f, gy + 1, gx)));
       }
     }
   } else {
@@ -445,24 +433,12 @@ k_stage(StageArgs a, StagePtrs p) {
       if (f < TZ) {
         fcx[f] = make_face(2, z0 + f, gy, gx, ahat_of(gcell(z0 + f, gy, gx - 1)), ahn);
         fcy[f] = make_face(1, z0 + f, gy, gx, ahat_of(gcell(z0 + f, gy - 1, gx)), ahn);
-        if (FUSED) {
-          // the upper faces: the same operands as the neighbours' lower faces
-          fcxu[f] = make_face(2, z0 + f, gy, gx + 1, ahn, ahat_of(gcell(z0 + f, gy, gx + 1)));
-          fcyu[f] = make_face(1, z0 + f, gy + 1, gx, ahn, ahat_of(gcell(z0 + f, gy + 1, gx)));
-        }
+        fcxu[f] = make_face(2, z0 + f, gy, gx + 1, ahn, ahat_of(gcell(z0 + f, gy, gx + 1)));
+        fcyu[f] = make_face(1, z0 + f, gy + 1, gx, ahn, ahat_of(gcell(z0 + f, gy + 1, gx)));
       }
       ahp = ahn;
     }
   }
-  // extra faces: the x face above the tile's last column on (row ty, plane
-  // lane) for lanes < TZ; the y face above its last row on (column tx, plane
-  // ty) for waves ty < TZ
-  const bool xe = tx < TZ, ye = ty < TZ;
-  const int zxe = z0 + (tx % TZ), zye = z0 + (ty % TZ);
-  const Face fcxe = make_face(2, zxe, gy, x0 + TX, ahat_of(gcell(zxe, gy, x0 + TX - 1)),
-                              ahat_of(gcell(zxe, gy, x0 + TX)));
-  const Face fcye = make_face(1, zye, y0 + TY, gx, ahat_of(gcell(zye, y0 + TY - 1, gx)),
-                              ahat_of(gcell(zye, y0 + TY, gx)));
 
   // ---- own-cell data used in the direction loop
   F bA[TZ], bB[TZ];                        // lazy map of the stage-2 base intensity
@@ -570,7 +546,7 @@ k_stage(StageArgs a, StagePtrs p) {
 
   for (int s = 0; s < ns; ++s) {
     const int buf = s & 1;
-    auto& pl = plb[FUSED ? buf : 0];
+    auto& pl = plb[buf];
     // direction components along i1 (z), i2 (y), i3 (x)
     const F nz = dirF[s], ny = dirF[ns + s], nx = dirF[2 * ns + s];
     // flat zero-incoming: the outside sides that receive zero for this direction
@@ -616,195 +592,76 @@ k_stage(StageArgs a, StagePtrs p) {
 
     F ddx[TZ], ddy[TZ];  // differences of the x and y face fluxes of the own cells
     F fz[TZ + 1];        // z faces of the column
-    if constexpr (!FUSED) {
-      // 2. half slopes, once per cell and axis: own cells (x, y from LDS, z from
-      // the window), plus the cells just outside the tile that its boundary
-      // faces need (x: lanes < 2 TZ, y: two rows shared over the waves)
+    // 2. half slopes and both faces of the own cells along every axis: x and y
+    // from the staged planes, z from the column window.  A face shared by two
+    // cells is evaluated by both threads from the same operands.
+    //
+    // With the cell values vm1 | v0 either side of a face and their half slopes
+    // hL, hR, the modified flux of Sec. 3.5 is
+    //   nu > 0:  nu (u (vm1 + hL) + v (v0 - hR) + d (vm1 - v0))
+    //   nu < 0:  nu (v (vm1 + hL) + u (v0 - hR) - d (vm1 - v0))
+    // plus the advection term aL (vm1 + hL) + aR (v0 - hR) for a moving fluid.
+    // Curved: the face record's gP, gN (one of them zero) and gA weight the two
+    // branches and the advection term.  Flat: the sign of the direction
+    // component is uniform over a face group, so each group takes one branch
+    // (POS); at rest nu is applied once per cell in the divergence.
+    auto fpos = [&](auto pos_tag, const Face& fc, int rec, F nu, F vm1, F hL, F v0, F hR) -> F {
+      constexpr int POS = decltype(pos_tag)::value;
+      const F L = vm1 + hL, Rr = v0 - hR, D = vm1 - v0;
+      F f;
+      if (CURVED) {
+        const F* r = GR + rec * 4;
+        f = r[0] * (fc.u * L + fc.v * Rr + fc.d * D) + r[1] * (fc.v * L + fc.u * Rr - fc.d * D);
+        if (MOVING) f += r[2] * (fc.aL * L + fc.aR * Rr);
+      } else {
+        f = POS ? fc.u * L + fc.v * Rr + fc.d * D : fc.v * L + fc.u * Rr - fc.d * D;
+        if (!NUOUT) f *= nu;
+        if (MOVING) f += fc.aL * L + fc.aR * Rr;
+      }
+      return f;
+    };
+    // upper minus lower face flux of the cell c2 from the values c0 .. c4 along the axis
+    auto div1 = [&](auto pos, const Face& lo, const Face& hi, int rlo, int rhi, F nu, F c0, F c1, F c2,
+                    F c3, F c4) -> F {
+      const F hm = half_slope<LIM>(c1 - c0, c2 - c1), h0 = half_slope<LIM>(c2 - c1, c3 - c2),
+              hp = half_slope<LIM>(c3 - c2, c4 - c3);
+      return fpos(pos, hi, rhi, nu, c2, h0, c3, hp) - fpos(pos, lo, rlo, nu, c1, hm, c2, h0);
+    };
+    auto xpart = [&](auto pos) {
+#pragma unroll
+      for (int k = 0; k < TZ; ++k)
+        ddx[k] = div1(pos, fcx[k], fcxu[k], k * TY + ty, k * TY + ty, nx, pl[k][ty + 2][tx],
+                      pl[k][ty + 2][tx + 1], w[k + 2], pl[k][ty + 2][tx + 3], pl[k][ty + 2][tx + 4]);
+    };
+    auto ypart = [&](auto pos) {
+#pragma unroll
+      for (int k = 0; k < TZ; ++k)
+        ddy[k] = div1(pos, fcy[k], fcyu[k], NRX + k * (TY + 1) + ty, NRX + k * (TY + 1) + ty + 1, ny,
+                      pl[k][ty][tx + 2], pl[k][ty + 1][tx + 2], w[k + 2], pl[k][ty + 3][tx + 2],
+                      pl[k][ty + 4][tx + 2]);
+    };
+    auto zpart = [&](auto pos) {
       F sz[NW];
-  #pragma unroll
-      for (int k = 0; k < TZ; ++k) {
-        const F v = w[k + 2];
-        hxs[k][ty][tx + 1] = half_slope<LIM>(v - pl[k][ty + 2][tx + 1], pl[k][ty + 2][tx + 3] - v);
-        hys[k][ty + 1][tx] = half_slope<LIM>(v - pl[k][ty + 1][tx + 2], pl[k][ty + 3][tx + 2] - v);
-      }
-  #pragma unroll
+#pragma unroll
       for (int j = 1; j <= TZ + 2; ++j) sz[j] = half_slope<LIM>(w[j] - w[j - 1], w[j + 1] - w[j]);
-      if (tx < 2 * TZ) {
-        const int k = tx >> 1, side = tx & 1;
-        const int c0 = side ? TX + 1 : 0;  // region columns of the cell's stencil
-        const F a0 = pl[k][ty + 2][c0], a1 = pl[k][ty + 2][c0 + 1], a2 = pl[k][ty + 2][c0 + 2];
-        hxs[k][ty][side ? TX + 1 : 0] = half_slope<LIM>(a1 - a0, a2 - a1);
-      }
-  #pragma unroll
-      for (int q = ty; q < 2 * TZ; q += TY) {
-        const int k = q >> 1, side = q & 1;
-        const int r0 = side ? TY + 1 : 0;  // region rows of the cell's stencil
-        const F a0 = pl[k][r0][tx + 2], a1 = pl[k][r0 + 1][tx + 2], a2 = pl[k][r0 + 2][tx + 2];
-        hys[k][side ? TY + 1 : 0][tx] = half_slope<LIM>(a1 - a0, a2 - a1);
-      }
-      __syncthreads();
-
-      // 3. face fluxes.  With the cell values vm1 | v0 either side of a face and
-      // their half slopes hL, hR, the modified flux of Sec. 3.5 is
-      //   nu > 0:  nu (u (vm1 + hL) + v (v0 - hR) + d (vm1 - v0))
-      //   nu < 0:  nu (v (vm1 + hL) + u (v0 - hR) - d (vm1 - v0))
-      // plus the advection term aL (vm1 + hL) + aR (v0 - hR) for a moving fluid.
-      // curved: gP, gN (one of them zero) and gA from the face's record; flat:
-      // the sign of the direction component is uniform over a face group, so
-      // each group takes one branch (POS) with weight nu (1 when it is applied
-      // in the divergence) and advection weight 1
-      auto flux = [&](auto pos_tag, const Face& fc, F gP, F gN, F gA, F vm1, F hL, F v0, F hR) -> F {
-        constexpr int POS = decltype(pos_tag)::value;
-        const F L = vm1 + hL, Rr = v0 - hR, D = vm1 - v0;
-        F f;
-        if (CURVED)
-          f = gP * (fc.u * L + fc.v * Rr + fc.d * D) + gN * (fc.v * L + fc.u * Rr - fc.d * D);
-        else if (NUOUT)
-          f = POS ? fc.u * L + fc.v * Rr + fc.d * D : fc.v * L + fc.u * Rr - fc.d * D;
-        else if (POS)
-          f = gP * (fc.u * L + fc.v * Rr + fc.d * D);
-        else
-          f = gP * (fc.v * L + fc.u * Rr - fc.d * D);
-        if (MOVING) f += gA * (fc.aL * L + fc.aR * Rr);
-        return f;
-      };
-      // weights of a face from its record (curved) or the direction component
-      auto weights = [&](int rec, F nu, F& gP, F& gN, F& gA) {
-        if (CURVED) {
-          const F* r = GR + rec * 4;
-          gP = r[0];
-          gN = r[1];
-          gA = r[2];
-        } else {
-          gP = nu;
-          gN = F(0);
-          gA = F(1);
-        }
-      };
-      auto xfaces = [&](auto pos) {
-        // x faces below each own cell; the extra one above the last column
-  #pragma unroll
-        for (int k = 0; k < TZ; ++k) {
-          F gP, gN, gA;
-          weights(k * TY + ty, nx, gP, gN, gA);
-          fxs[k][ty][tx] = flux(pos, fcx[k], gP, gN, gA, pl[k][ty + 2][tx + 1], hxs[k][ty][tx], w[k + 2],
-                                hxs[k][ty][tx + 1]);
-        }
-        if (xe) {
-          const int k = tx % TZ;
-          F gP, gN, gA;
-          weights(k * TY + ty, nx, gP, gN, gA);
-          fxs[k][ty][TX] = flux(pos, fcxe, gP, gN, gA, pl[k][ty + 2][TX + 1], hxs[k][ty][TX],
-                                pl[k][ty + 2][TX + 2], hxs[k][ty][TX + 1]);
-        }
-      };
-      auto yfaces = [&](auto pos) {
-        // y faces below each own cell; the extra one above the last row
-  #pragma unroll
-        for (int k = 0; k < TZ; ++k) {
-          F gP, gN, gA;
-          weights(NRX + k * (TY + 1) + ty, ny, gP, gN, gA);
-          fys[k][ty][tx] = flux(pos, fcy[k], gP, gN, gA, pl[k][ty + 1][tx + 2], hys[k][ty][tx], w[k + 2],
-                                hys[k][ty + 1][tx]);
-        }
-        if (ye) {
-          const int k = ty % TZ;
-          F gP, gN, gA;
-          weights(NRX + k * (TY + 1) + TY, ny, gP, gN, gA);
-          fys[k][TY][tx] = flux(pos, fcye, gP, gN, gA, pl[k][TY + 1][tx + 2], hys[k][TY][tx],
-                                pl[k][TY + 2][tx + 2], hys[k][TY + 1][tx]);
-        }
-      };
-      auto zfaces = [&](auto pos) {
-        // z faces of the column, from registers
-  #pragma unroll
-        for (int f = 0; f <= TZ; ++f) {
-          F gP, gN, gA;
-          weights(NRX + NRY + f * TY + ty, nz, gP, gN, gA);
-          fz[f] = flux(pos, fcz[f], gP, gN, gA, w[f + 1], sz[f + 1], w[f + 2], sz[f + 2]);
-        }
-      };
-      using TPos = std::integral_constant<int, 1>;
-      using TNeg = std::integral_constant<int, 0>;
-      if (CURVED) {
-        xfaces(TPos{});
-        yfaces(TPos{});
-        zfaces(TPos{});
-      } else {
-        auto up = [](F nu) { return __builtin_amdgcn_readfirstlane(nu > F(0) ? 1 : 0) != 0; };
-        if (up(nx)) xfaces(TPos{}); else xfaces(TNeg{});
-        if (up(ny)) yfaces(TPos{}); else yfaces(TNeg{});
-        if (up(nz)) zfaces(TPos{}); else zfaces(TNeg{});
-      }
-      __syncthreads();
 #pragma unroll
-      for (int k = 0; k < TZ; ++k) {
-        ddx[k] = fxs[k][ty][tx + 1] - fxs[k][ty][tx];
-        ddy[k] = fys[k][ty + 1][tx] - fys[k][ty][tx];
-      }
+      for (int f = 0; f <= TZ; ++f)
+        fz[f] = fpos(pos, fcz[f], NRX + NRY + f * TY + ty, nz, w[f + 1], sz[f + 1], w[f + 2], sz[f + 2]);
+    };
+    using TPos = std::integral_constant<int, 1>;
+    using TNeg = std::integral_constant<int, 0>;
+    if (CURVED) {
+      xpart(TPos{});
+      ypart(TPos{});
+      zpart(TPos{});
     } else {
-      // 2'. slopes and both faces of the own cells along every axis: x and y
-      // from the staged planes, z from the column window.  A face shared by
-      // two cells is evaluated by both threads from the same operands.
-      // the modified flux of Sec. 3.5 through one face (see the unfused path)
-      auto fpos = [&](auto pos_tag, const Face& fc, int rec, F nu, F vm1, F hL, F v0, F hR) -> F {
-        constexpr int POS = decltype(pos_tag)::value;
-        const F L = vm1 + hL, Rr = v0 - hR, D = vm1 - v0;
-        F f;
-        if (CURVED) {
-          const F* r = GR + rec * 4;
-          f = r[0] * (fc.u * L + fc.v * Rr + fc.d * D) + r[1] * (fc.v * L + fc.u * Rr - fc.d * D);
-          if (MOVING) f += r[2] * (fc.aL * L + fc.aR * Rr);
-        } else {
-          f = POS ? fc.u * L + fc.v * Rr + fc.d * D : fc.v * L + fc.u * Rr - fc.d * D;
-          if (!NUOUT) f *= nu;
-          if (MOVING) f += fc.aL * L + fc.aR * Rr;
-        }
-        return f;
-      };
-      // upper minus lower face flux of the cell c2 from the values c0 .. c4 along the axis
-      auto div1 = [&](auto pos, const Face& lo, const Face& hi, int rlo, int rhi, F nu, F c0, F c1, F c2,
-                      F c3, F c4) -> F {
-        const F hm = half_slope<LIM>(c1 - c0, c2 - c1), h0 = half_slope<LIM>(c2 - c1, c3 - c2),
-                hp = half_slope<LIM>(c3 - c2, c4 - c3);
-        return fpos(pos, hi, rhi, nu, c2, h0, c3, hp) - fpos(pos, lo, rlo, nu, c1, hm, c2, h0);
-      };
-      auto xpart = [&](auto pos) {
-#pragma unroll
-        for (int k = 0; k < TZ; ++k)
-          ddx[k] = div1(pos, fcx[k], fcxu[k], k * TY + ty, k * TY + ty, nx, pl[k][ty + 2][tx],
-                        pl[k][ty + 2][tx + 1], w[k + 2], pl[k][ty + 2][tx + 3], pl[k][ty + 2][tx + 4]);
-      };
-      auto ypart = [&](auto pos) {
-#pragma unroll
-        for (int k = 0; k < TZ; ++k)
-          ddy[k] = div1(pos, fcy[k], fcyu[k], NRX + k * (TY + 1) + ty, NRX + k * (TY + 1) + ty + 1, ny,
-                        pl[k][ty][tx + 2], pl[k][ty + 1][tx + 2], w[k + 2], pl[k][ty + 3][tx + 2],
-                        pl[k][ty + 4][tx + 2]);
-      };
-      auto zpart = [&](auto pos) {
-        F sz[NW];
-#pragma unroll
-        for (int j = 1; j <= TZ + 2; ++j) sz[j] = half_slope<LIM>(w[j] - w[j - 1], w[j + 1] - w[j]);
-#pragma unroll
-        for (int f = 0; f <= TZ; ++f)
-          fz[f] = fpos(pos, fcz[f], NRX + NRY + f * TY + ty, nz, w[f + 1], sz[f + 1], w[f + 2], sz[f + 2]);
-      };
-      if (CURVED) {
-        xpart(std::integral_constant<int, 1>{});
-        ypart(std::integral_constant<int, 1>{});
-        zpart(std::integral_constant<int, 1>{});
-      } else {
-      using TPos = std::integral_constant<int, 1>;
-      using TNeg = std::integral_constant<int, 0>;
       auto up = [](F nu) { return __builtin_amdgcn_readfirstlane(nu > F(0) ? 1 : 0) != 0; };
       if (up(nx)) xpart(TPos{}); else xpart(TNeg{});
       if (up(ny)) ypart(TPos{}); else ypart(TNeg{});
       if (up(nz)) zpart(TPos{}); else zpart(TNeg{});
-      }
     }
 
-    // 4. divergence, update, interaction sums
+    // 3. divergence, update, interaction sums
     const double ws = p.w[s];
     const F cz = NUOUT ? h * nz * idx0 : h * idx0, cy = NUOUT ? h * ny * idx1 : h * idx1,
             cx = NUOUT ? h * nx * idx2 : h * idx2;
@@ -1146,8 +1003,8 @@ hipError_t launch_stage(rt_ctx* c, const StageArgs& a, const StagePtrs& p, bool 
                         hipStream_t st) {
   const bool mc = a.limiter == RT_LIM_MC;
   // the moving-fluid and curved forms carry more per-cell state (the fluid
-  // velocity, advection weights, records): two cells per column keep them in
-  // registers
+  // velocity, advection weights, records): two cells per column (one in FP64)
+  // keep them in registers
   const bool mv = c->moving || c->curved;
   if (c->fp32 && mv)
     return mc ? launch_tiled<float, float, 2, RT_LIM_MC, true>(c, a, p, stage2, st)
@@ -1156,8 +1013,8 @@ hipError_t launch_stage(rt_ctx* c, const StageArgs& a, const StagePtrs& p, bool 
     return mc ? launch_tiled<float, float, 4, RT_LIM_MC, false>(c, a, p, stage2, st)
               : launch_tiled<float, float, 4, RT_LIM_MINMOD, false>(c, a, p, stage2, st);
   if (mv)
-    return mc ? launch_tiled<double, double, 2, RT_LIM_MC, true>(c, a, p, stage2, st)
-              : launch_tiled<double, double, 2, RT_LIM_MINMOD, true>(c, a, p, stage2, st);
+    return mc ? launch_tiled<double, double, 1, RT_LIM_MC, true>(c, a, p, stage2, st)
+              : launch_tiled<double, double, 1, RT_LIM_MINMOD, true>(c, a, p, stage2, st);
   return mc ? launch_tiled<double, double, 2, RT_LIM_MC, false>(c, a, p, stage2, st)
             : launch_tiled<double, double, 2, RT_LIM_MINMOD, false>(c, a, p, stage2, st);
 }
