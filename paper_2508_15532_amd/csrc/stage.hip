@@ -201,8 +201,9 @@ __device__ Solve solve_cell(const StageArgs& a, double r, double T0, double aa, 
 // ---------------------------------------------------------------------------
 // the fused stage kernel
 //
-// Work decomposition.  A workgroup of 256 threads owns a tile of 64 (i3, x) x
-// 4 (i2, y) x TZ (i1, z) cells and loops over all directions.  Wave ty owns row
+// Work decomposition.  A workgroup of 64 TY threads owns a tile of 64 (i3, x) x
+// TY (i2, y) x TZ (i1, z) cells and loops over all directions (TY = 8 at rest,
+// 4 with a moving fluid, whose threads hold more state).  Wave ty owns row
 // y0 + ty, lane tx column x0 + tx, and each thread the TZ cells of its column
 // along z.  For each direction:
 //   1. the thread's column with a two-cell halo along z lives in registers
@@ -220,9 +221,9 @@ __device__ Solve solve_cell(const StageArgs& a, double r, double T0, double aa, 
 // cells and writes the cell's interaction map.
 // ---------------------------------------------------------------------------
 template <typename S, typename F, int TZ, bool STAGE2, bool MOVING, int LIM, bool CURVED>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2)))
 k_stage(StageArgs a, StagePtrs p) {
-  constexpr int TY = 4, NT = TX * TY;
+  constexpr int TY = !MOVING ? 8 : 4, NT = TX * TY;  // rows per tile (one per wave), threads
   constexpr int RX = TX + 4, RY = TY + 4;
   constexpr int NW = TZ + 4;  // column window: planes z0-2 .. z0+TZ+1
   static_assert(4 * TZ <= TX, "the x halo takes four lanes per plane");
@@ -319,6 +320,7 @@ k_stage(StageArgs a, StagePtrs p) {
     else wflag |= (unsigned long long)f << (6 * j);
   }
   // y halo: row hr = ty of {y0-2, y0-1, y0+TY, y0+TY+1} for the TZ own planes
+  const bool yh = ty < 4;                  // the four waves that load the y halo rows
   const int hry = ty < 2 ? ty : TY + ty;  // region row
   const int hgy = y0 - 2 + hry;
   int ycell[TZ];
@@ -513,7 +515,7 @@ k_stage(StageArgs a, StagePtrs p) {
 #pragma unroll
     for (int j = 0; j < NW; ++j) pw[j] = ld(Is, woff[j], wcell[j]);
 #pragma unroll
-    for (int k = 0; k < TZ; ++k) py[k] = ld(Is, yoff[k], ycell[k]);
+    for (int k = 0; k < TZ; ++k) py[k] = yh ? ld(Is, yoff[k], ycell[k]) : S(0);
     px = ld(Is, xoff, xcell);
     if (STAGE2) {
       const S* Ib = Ibase + (long long)s * nc;
@@ -576,8 +578,10 @@ k_stage(StageArgs a, StagePtrs p) {
     }
 #pragma unroll
     for (int k = 0; k < TZ; ++k) pl[k][ty + 2][tx + 2] = w[k + 2];
+    if (yh) {
 #pragma unroll
-    for (int k = 0; k < TZ; ++k) pl[k][hry][tx + 2] = yv[k];
+      for (int k = 0; k < TZ; ++k) pl[k][hry][tx + 2] = yv[k];
+    }
     if (xh) pl[hk][ty + 2][hrx] = xv;
     F base[TZ], dang[CURVED ? TZ : 1];
 #pragma unroll
@@ -978,7 +982,7 @@ hipError_t launch_ordered(rt_ctx* c, Kern kern, StageArgs a, StagePtrs p, int TY
 // MOVE: the moving-fluid family (moving fluid or curved geometry), else at rest
 template <typename S, typename F, int TZ, int LIM, bool MOVE>
 hipError_t launch_tiled(rt_ctx* c, StageArgs a, const StagePtrs& p, bool stage2, hipStream_t st) {
-  constexpr int TY = 4;
+  constexpr int TY = !MOVE ? 8 : 4;  // as in k_stage
   a.tiles_x = (c->n[2] + TX - 1) / TX;
   a.tiles_y = (c->n[1] + TY - 1) / TY;
   a.tiles_z = (c->n[0] + TZ - 1) / TZ;
