@@ -481,7 +481,8 @@ rt_status rt_step(rt_ctx* c, void* I, double* T, double dt, int nsteps, double* 
     RT_HIP(timed(c, RT_K_STAGE2, stream, [&] { return launch_stage(c, a, p, true, stream); }));
     if (c->moving) {
       RT_HIP(timed(c, RT_K_MATERIALIZE, stream, [&] {
-        return launch_materialize(c, I, c->d_mapA, dt, R_out, last ? G_out : nullptr, stream);
+        return launch_materialize(c, I, c->d_mapA, dt, last ? R_out : nullptr, last ? G_out : nullptr,
+                                  stream);
       }));
       mapA = nullptr;
     } else {
