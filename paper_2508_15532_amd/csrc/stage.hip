@@ -1,8 +1,9 @@
-// Fused stage kernel of the flat-metric step: per-face flux coefficients,
-// PLI transport of every direction, and the per-cell sums and implicit
-// temperature solve of the interaction, in one pass over the intensities.
+// Fused stage kernel of the predictor-corrector step (flat and curved
+// metrics): per-face flux coefficients, PLI transport of every direction, and
+// the per-cell sums and implicit temperature solve of the interaction, in one
+// pass over the intensities.
 //
-// Work decomposition: see the kernel below (64 x 4 x TZ cell tiles, a column
+// Work decomposition: see the kernel below (64 x TY x TZ cell tiles, a column
 // of TZ cells per thread, all directions looped inside the workgroup).
 //
 // Lazy interaction.  At rest the implicit update of a cell is affine in the
@@ -319,7 +320,7 @@ k_stage(StageArgs a, StagePtrs p) {
     if (CURVED) wzoff[j] = zi_offset(f, gz, gy, gx);
     else wflag |= (unsigned long long)f << (6 * j);
   }
-  // y halo: row hr = ty of {y0-2, y0-1, y0+TY, y0+TY+1} for the TZ own planes
+  // y halo: waves 0..3 load row ty of {y0-2, y0-1, y0+TY, y0+TY+1} for the TZ own planes
   const bool yh = ty < 4;                  // the four waves that load the y halo rows
   const int hry = ty < 2 ? ty : TY + ty;  // region row
   const int hgy = y0 - 2 + hry;
