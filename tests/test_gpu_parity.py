@@ -179,6 +179,29 @@ def test_restart_equals_continuous_run():
     ctx.close()
 
 
+@pytest.mark.parametrize("moving", [False, True])
+def test_multi_step_call_returns_last_moments(moving):
+    """One call of 3 steps equals 3 calls of one step bitwise, including the
+    moments R and the 4-force G that the call returns for its last step."""
+    n = (6, 5, 70)
+    wl = W.brems_flat(n=n, generation=1, seed=9)
+    if moving:
+        wl["u"] = moving_fluid(n, 19)
+    ctx = gpu_context(wl)
+    I, T = gpu_initial(ctx, wl)
+    I2, T2 = I.clone(), T.clone()
+    R, G = (torch.zeros((k, ctx.nc), dtype=F64, device=I.device) for k in (10, 4))
+    R2, G2 = torch.zeros_like(R), torch.zeros_like(G)
+    _say(f"multi-step call, moving={moving}")
+    ctx.step(I, T, wl["dt"], 3, G=G, R=R)
+    for _ in range(3):
+        ctx.step(I2, T2, wl["dt"], 1, G=G2, R=R2)
+    torch.cuda.synchronize()
+    assert torch.equal(I, I2) and torch.equal(T, T2)
+    assert torch.equal(R, R2) and torch.equal(G, G2)
+    ctx.close()
+
+
 # --------------------------------------------------------------------------
 # full-size flat workload (128^3 x 162), in the launch configuration of bench.py
 # --------------------------------------------------------------------------
