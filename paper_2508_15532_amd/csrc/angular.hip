@@ -27,17 +27,19 @@ namespace {
 
 // D'_s(c) = A_s0 I_s(c) + sum_j A_sj I_(o_sj)(c) over the KS_DEG padded
 // neighbours o_sj of s, with the per-(r, theta) coefficients A (scaled to the
-// update on the host).  CW cells along phi per workgroup; with CW = 64 a wave
-// owns one direction at a time, so its coefficient row and neighbour list are
-// wave-uniform and come in as a few wide scalar loads, independent of the
-// intensities, so that they overlap the LDS reads of the previous direction.
+// update on the host).  CW cells along phi per workgroup, 256 / CW groups of
+// CW threads; a thread keeps one cell (t % CW) throughout and its group takes
+// every (256 / CW)-th direction, so a load's address advances by a uniform
+// stride and the LDS slots by immediate offsets.
 template <typename S, int CW>
 __global__ void __launch_bounds__(256)
 k_angular(long long nc, int n3, int ns, const S* __restrict__ I, S* __restrict__ D,
           const S* __restrict__ coef, const int* __restrict__ nbr) {
+  constexpr int NGRP = 256 / CW;
   extern __shared__ unsigned char smem_raw[];
   // LDS: the run's intensities [ns][CW], its coefficient rows [ns][KS_ROW] and
-  // the neighbour lists [ns][KS_ROW] (16-bit direction numbers)
+  // the neighbour lists [ns][KS_ROW] as byte offsets of the neighbours' rows
+  // in the intensity block (16 bits: ns CW elem < 64 KiB)
   S* col = reinterpret_cast<S*>(smem_raw);
   S* lco = col + ns * CW;
   unsigned short* lnb = reinterpret_cast<unsigned short*>(lco + ns * KS_ROW);
@@ -47,45 +49,45 @@ k_angular(long long nc, int n3, int ns, const S* __restrict__ I, S* __restrict__
   const long long cbase = row * n3 + x0;
   const int t = threadIdx.x;
   const int ncol = min(CW, n3 - x0);
+  const int l = t % CW;
+  int grp = t / CW;
+  if (CW == 64) grp = __builtin_amdgcn_readfirstlane(grp);
+  const bool inrun = l < ncol;
   // the coefficient rows and neighbour lists go to LDS first; their reads
   // overlap those of the intensities
   const S* A = coef + row * (long long)ns * KS_ROW;
   for (int k = t; k < ns * KS_ROW; k += 256) {
     lco[k] = A[k];
-    lnb[k] = (unsigned short)nbr[k];
+    lnb[k] = (unsigned short)(nbr[k] * CW * (int)sizeof(S));
   }
-  // one or two batches of independent loads per thread: the whole run is in
-  // flight at once
+  // this thread's cell in every direction of its group (cells past the run
+  // re-read the run's last cell and stage zeros)
+  const S* src = I + (long long)grp * nc + cbase + min(l, ncol - 1);
+  const long long stride = (long long)NGRP * nc;
+  const int nper = (ns - grp + NGRP - 1) / NGRP;  // directions of this group
+  // batches of B loads per thread: the run is in flight at once
   constexpr int B = CW >= 64 ? 48 : 24;
-  const int total = ns * CW;
-  for (int k0 = t; k0 < total; k0 += B * 256) {
+  for (int u0 = 0; u0 < nper; u0 += B) {
     S v[B];
 #pragma unroll
-    for (int u = 0; u < B; ++u) {
-      // clamped indices keep every load in bounds, so none needs a branch
-      const int k = min(k0 + u * 256, total - 1);
-      const int s = k / CW, l = k % CW;
-      const S x = I[(long long)s * nc + cbase + min(l, ncol - 1)];
-      v[u] = l < ncol ? x : S(0);
-    }
+    for (int u = 0; u < B; ++u) v[u] = src[min(u0 + u, nper - 1) * stride];
 #pragma unroll
     for (int u = 0; u < B; ++u)
-      if (k0 + u * 256 < total) col[k0 + u * 256] = v[u];
+      if (u0 + u < nper) col[(grp + (u0 + u) * NGRP) * CW + l] = inrun ? v[u] : S(0);
   }
   __syncthreads();
-  const int l = t % CW;
-  constexpr int NGRP = 256 / CW;
-  int grp = t / CW;
-  if (CW == 64) grp = __builtin_amdgcn_readfirstlane(grp);
   static_assert(KS_DEG + 1 <= KS_ROW, "row layout");
+  const char* lane = reinterpret_cast<const char*>(col + l);
+  S* dst = D + (long long)grp * nc + cbase + l;
 #pragma unroll 2
   for (int s = grp; s < ns; s += NGRP) {
     const S* a = lco + s * KS_ROW;
     const unsigned short* o = lnb + s * KS_ROW;
     S acc = a[0] * col[s * CW + l];
 #pragma unroll
-    for (int j = 1; j <= KS_DEG; ++j) acc += a[j] * col[o[j] * CW + l];
-    if (l < ncol) D[(long long)s * nc + cbase + l] = acc;
+    for (int j = 1; j <= KS_DEG; ++j) acc += a[j] * *reinterpret_cast<const S*>(lane + o[j]);
+    if (inrun) *dst = acc;
+    dst += stride;
   }
 }
 

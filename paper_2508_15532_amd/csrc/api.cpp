@@ -132,7 +132,8 @@ rt_status set_kerr_schild(rt_ctx* c, double M, double a, double cfl) {
   // within 40 KiB (four workgroups per compute unit); at least one cell within 64 KiB
   int cw = 32;
   while (cw > 1 && angular_lds_bytes(c->ns, cw, c->elem) > 40960) cw /= 2;
-  if (angular_lds_bytes(c->ns, cw, c->elem) > 65536)
+  // (the kernel keeps 16-bit byte offsets into the run's intensity block)
+  if (angular_lds_bytes(c->ns, cw, c->elem) > 65536 || (size_t)c->ns * cw * c->elem > 65535)
     return fail(RT_E_ARG, "rt_set_metric: too many directions for the curved form");
   c->ks_cw = cw;
   c->ks_ninc = T.inc_off[c->ns];
