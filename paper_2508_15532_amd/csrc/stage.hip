@@ -110,11 +110,6 @@ __device__ __forceinline__ void opac(const StageArgs& a, const double* __restric
 // Dc = f2 f4/(f2+f4): P = E Wu + Dc, Q = E Wd - Dc, U = E Wu/2, V = E Wd/2.
 // With a moving fluid the advection term (1-E)(max(vL,0) I_L + min(vR,0) I_R)
 // adds aL = (1-E) max(vL,0), aR = (1-E) min(vR,0).
-template <typename F>
-struct FaceC {
-  F P, Q, U, V;
-};
-
 __device__ __forceinline__ void face_coefs(double tau, double& P, double& Q, double& U, double& V,
                                            double& E) {
   E = exp(-tau);
