@@ -31,15 +31,19 @@ namespace {
 // CW threads; a thread keeps one cell (t % CW) throughout and its group takes
 // every (256 / CW)-th direction, so a load's address advances by a uniform
 // stride and the LDS slots by immediate offsets.
-template <typename S, int CW>
+// LCO: the position's coefficient rows and the neighbour lists are staged in
+// LDS too (few directions); without it (many directions, e.g. 642) the LDS
+// holds only the intensities, so that the run stays long, and the rows and
+// lists are read from memory, where every group of the workgroup shares them.
+template <typename S, int CW, bool LCO>
 __global__ void __launch_bounds__(256)
 k_angular(long long nc, int n3, int ns, const S* __restrict__ I, S* __restrict__ D,
           const S* __restrict__ coef, const int* __restrict__ nbr) {
   constexpr int NGRP = 256 / CW;
   extern __shared__ unsigned char smem_raw[];
-  // LDS: the run's intensities [ns][CW], its coefficient rows [ns][KS_ROW] and
-  // the neighbour lists [ns][KS_ROW] as byte offsets of the neighbours' rows
-  // in the intensity block (16 bits: ns CW elem < 64 KiB)
+  // LDS: the run's intensities [ns][CW] and, with LCO, its coefficient rows
+  // [ns][KS_ROW] and the neighbour lists [ns][KS_ROW] as byte offsets of the
+  // neighbours' rows in the intensity block (16 bits: ns CW elem < 64 KiB)
   S* col = reinterpret_cast<S*>(smem_raw);
   S* lco = col + ns * CW;
   unsigned short* lnb = reinterpret_cast<unsigned short*>(lco + ns * KS_ROW);
@@ -56,10 +60,11 @@ k_angular(long long nc, int n3, int ns, const S* __restrict__ I, S* __restrict__
   // the coefficient rows and neighbour lists go to LDS first; their reads
   // overlap those of the intensities
   const S* A = coef + row * (long long)ns * KS_ROW;
-  for (int k = t; k < ns * KS_ROW; k += 256) {
-    lco[k] = A[k];
-    lnb[k] = (unsigned short)(nbr[k] * CW * (int)sizeof(S));
-  }
+  if (LCO)
+    for (int k = t; k < ns * KS_ROW; k += 256) {
+      lco[k] = A[k];
+      lnb[k] = (unsigned short)(nbr[k] * CW * (int)sizeof(S));
+    }
   // this thread's cell in every direction of its group (cells past the run
   // re-read the run's last cell and stage zeros)
   const S* src = I + (long long)grp * nc + cbase + min(l, ncol - 1);
@@ -81,11 +86,20 @@ k_angular(long long nc, int n3, int ns, const S* __restrict__ I, S* __restrict__
   S* dst = D + (long long)grp * nc + cbase + l;
 #pragma unroll 2
   for (int s = grp; s < ns; s += NGRP) {
-    const S* a = lco + s * KS_ROW;
-    const unsigned short* o = lnb + s * KS_ROW;
-    S acc = a[0] * col[s * CW + l];
+    S acc;
+    if (LCO) {
+      const S* a = lco + s * KS_ROW;
+      const unsigned short* o = lnb + s * KS_ROW;
+      acc = a[0] * col[s * CW + l];
 #pragma unroll
-    for (int j = 1; j <= KS_DEG; ++j) acc += a[j] * *reinterpret_cast<const S*>(lane + o[j]);
+      for (int j = 1; j <= KS_DEG; ++j) acc += a[j] * *reinterpret_cast<const S*>(lane + o[j]);
+    } else {
+      const S* a = A + s * KS_ROW;
+      const int* o = nbr + s * KS_ROW;
+      acc = a[0] * col[s * CW + l];
+#pragma unroll
+      for (int j = 1; j <= KS_DEG; ++j) acc += a[j] * col[o[j] * CW + l];
+    }
     if (inrun) *dst = acc;
     dst += stride;
   }
@@ -96,19 +110,28 @@ hipError_t launch_cw(rt_ctx* c, const void* I, hipStream_t st) {
   const long long nrt = (long long)c->n[0] * c->n[1];
   const int cw = c->ks_cw;
   const dim3 grid((unsigned)(nrt * ((c->n[2] + cw - 1) / cw))), block(256);
-  const size_t lds = angular_lds_bytes(c->ns, cw, sizeof(S));
+  const bool lco = c->ks_lco;
+  const size_t lds = angular_lds_bytes(c->ns, cw, sizeof(S), lco);
   const S* in = (const S*)I;
   S* out = (S*)c->d_angD;
   const S* A = (const S*)c->d_acoef;
+#define RT_ANG(CW)                                                                                      \
+  if (lco)                                                                                              \
+    hipLaunchKernelGGL((k_angular<S, CW, true>), grid, block, lds, st, c->nc, c->n[2], c->ns, in, out, A, \
+                       c->d_inc);                                                                       \
+  else                                                                                                  \
+    hipLaunchKernelGGL((k_angular<S, CW, false>), grid, block, lds, st, c->nc, c->n[2], c->ns, in, out, A, \
+                       c->d_inc)
   switch (cw) {
-    case 64: hipLaunchKernelGGL((k_angular<S, 64>), grid, block, lds, st, c->nc, c->n[2], c->ns, in, out, A, c->d_inc); break;
-    case 32: hipLaunchKernelGGL((k_angular<S, 32>), grid, block, lds, st, c->nc, c->n[2], c->ns, in, out, A, c->d_inc); break;
-    case 16: hipLaunchKernelGGL((k_angular<S, 16>), grid, block, lds, st, c->nc, c->n[2], c->ns, in, out, A, c->d_inc); break;
-    case 8: hipLaunchKernelGGL((k_angular<S, 8>), grid, block, lds, st, c->nc, c->n[2], c->ns, in, out, A, c->d_inc); break;
-    case 4: hipLaunchKernelGGL((k_angular<S, 4>), grid, block, lds, st, c->nc, c->n[2], c->ns, in, out, A, c->d_inc); break;
-    case 2: hipLaunchKernelGGL((k_angular<S, 2>), grid, block, lds, st, c->nc, c->n[2], c->ns, in, out, A, c->d_inc); break;
-    default: hipLaunchKernelGGL((k_angular<S, 1>), grid, block, lds, st, c->nc, c->n[2], c->ns, in, out, A, c->d_inc); break;
+    case 64: RT_ANG(64); break;
+    case 32: RT_ANG(32); break;
+    case 16: RT_ANG(16); break;
+    case 8: RT_ANG(8); break;
+    case 4: RT_ANG(4); break;
+    case 2: RT_ANG(2); break;
+    default: RT_ANG(1); break;
   }
+#undef RT_ANG
   return hipGetLastError();
 }
 

@@ -128,13 +128,22 @@ rt_status set_kerr_schild(rt_ctx* c, double M, double a, double cfl) {
   } catch (const std::exception& e) {
     return fail(RT_E_ARG, std::string("rt_set_metric: ") + e.what());
   }
-  // angular kernel: runs of up to 32 phi cells, as long as the run's LDS stays
-  // within 40 KiB (four workgroups per compute unit); at least one cell within 64 KiB
+  // angular kernel: runs of up to 32 phi cells with the coefficient rows in LDS
+  // as long as the run's LDS stays within 40 KiB (four workgroups per compute
+  // unit) and the run keeps at least 16 cells; with more directions the LDS
+  // holds only the intensities of runs of up to 64 cells within 48 KiB
   int cw = 32;
-  while (cw > 1 && angular_lds_bytes(c->ns, cw, c->elem) > 40960) cw /= 2;
+  bool lco = true;
+  while (cw > 16 && angular_lds_bytes(c->ns, cw, c->elem, true) > 40960) cw /= 2;
+  if (angular_lds_bytes(c->ns, cw, c->elem, true) > 40960) {
+    lco = false;
+    cw = 64;
+    while (cw > 1 && angular_lds_bytes(c->ns, cw, c->elem, false) > 49152) cw /= 2;
+  }
   // (the kernel keeps 16-bit byte offsets into the run's intensity block)
-  if (angular_lds_bytes(c->ns, cw, c->elem) > 65536 || (size_t)c->ns * cw * c->elem > 65535)
+  if (angular_lds_bytes(c->ns, cw, c->elem, lco) > 65536 || (size_t)c->ns * cw * c->elem > 65535)
     return fail(RT_E_ARG, "rt_set_metric: too many directions for the curved form");
+  c->ks_lco = lco;
   c->ks_cw = cw;
   c->ks_ninc = T.inc_off[c->ns];
   c->ks_zin_stride = T.zin_stride;

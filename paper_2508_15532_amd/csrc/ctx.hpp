@@ -27,6 +27,7 @@ struct rt_ctx {
   // Kerr-Schild tables on the device (curved geometry; NULL when flat)
   bool curved = false;
   int ks_ninc = 0, ks_zin_stride = 0, ks_cw = 64;
+  bool ks_lco = true;  // angular kernel: coefficient rows staged in LDS
   void* d_rec_r = nullptr;       // [ns][(N1+1) N2][4] transport type
   void* d_rec_t = nullptr;       // [ns][N1 (N2+1)][4]
   void* d_rec_p = nullptr;       // [ns][N1 N2][4]
@@ -87,10 +88,10 @@ namespace rt {
 // angular coupling of the curved geometry: a direction of the geodesic grid
 // has at most KS_DEG neighbours; its coefficient row holds KS_ROW entries
 constexpr int KS_DEG = 6, KS_ROW = 8;
-// LDS of the angular kernel for a run of cw cells: intensities, coefficient
-// rows and 16-bit neighbour lists
-inline size_t angular_lds_bytes(int ns, int cw, size_t elem) {
-  return (size_t)ns * cw * elem + (size_t)ns * KS_ROW * elem + (size_t)ns * KS_ROW * 2;
+// LDS of the angular kernel for a run of cw cells: intensities and, when lco,
+// the coefficient rows and 16-bit neighbour lists
+inline size_t angular_lds_bytes(int ns, int cw, size_t elem, bool lco) {
+  return (size_t)ns * cw * elem + (lco ? (size_t)ns * KS_ROW * (elem + 2) : 0);
 }
 
 void set_error(const std::string& msg);

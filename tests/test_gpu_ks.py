@@ -176,9 +176,10 @@ def test_ks_full_size_fp32_sampled():
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_ks_generation3(precision):
-    """642 directions: the angular kernel holds fewer phi cells per workgroup
-    (8 in FP64, 16 in FP32) so that all directions fit its LDS; 5 x 8 x 20
-    cells, so a phi row spans several workgroups with a ragged last one."""
+    """642 directions: the angular kernel keeps only the intensities in LDS
+    (runs of 8 phi cells in FP64, 16 in FP32) and reads the coefficient rows
+    from memory; 5 x 8 x 20 cells, so a phi row spans several workgroups with a
+    ragged last one."""
     wl, I0 = _case(n=(5, 8, 20), generation=3, pole_rows=1)
     _say(f"torus_ks {precision} g3 5x8x20 2 steps")
     g = gpu_run(wl, 2, precision=precision, I0=I0)
