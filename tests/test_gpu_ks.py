@@ -174,6 +174,66 @@ def test_ks_full_size_fp32_sampled():
         assert rel_l2(Tg[lo1:hi1, lo2:hi2][inner], o["T"][inner]) < 1e-5
 
 
+def test_ks_c5_full_size_fp32_sampled():
+    """The a = 0.9 turbulent torus at 384x192x128, generation 3 (642
+    directions), lognormal density (sigma_ln 0.7) and scattering, FP32: one
+    step on the full grid (24 GB per intensity copy, the angular kernel in its
+    many-direction form), then sub-boxes away from the r and theta boundaries
+    recomputed by the oracle with a 4-cell halo and compared on their
+    interiors.  The initial intensity is a seeded rank-2 product a_s b_c + a'_s b'_c
+    (built on the GPU, sliced on the host, the same float32 arithmetic)."""
+    n = (384, 192, 128)
+    gen, ns = 3, 642
+    wl = W.torus_ks(n=n, generation=gen, sigma_ln=0.7, scattering=True)
+    rng = np.random.default_rng(31)
+    nc = n[0] * n[1] * n[2]
+    a1, a2 = (rng.uniform(0.2, 1.0, ns).astype(np.float32) for _ in range(2))
+    b1, b2 = (rng.uniform(0.2, 1.0, nc).astype(np.float32) for _ in range(2))
+    ctx = gpu_context(wl, precision="fp32")
+    dt = ctx.dt_max
+    _say(f"torus_ks fp32 384x192x128 g3 sigma_ln 0.7 scattering, 1 step dt={dt}")
+    dev = torch.device("cuda", 0)
+    A1, A2 = (torch.as_tensor(x, device=dev)[:, None] for x in (a1, a2))
+    B1, B2 = (torch.as_tensor(x, device=dev)[None, :] for x in (b1, b2))
+    I = (A1 * B1 + A2 * B2).contiguous()
+    del A1, A2, B1, B2
+    T = torch.as_tensor(wl["T"], dtype=F64).reshape(-1).to(dev).contiguous()
+    ctx.step(I, T, dt, 1)
+    torch.cuda.synchronize()
+    Tg = T.cpu().reshape(n)
+    I4 = I.view(ns, *n)
+    _, wgt, _ = __import__("paper_2508_15532_amd").geodesic_grid(gen)
+    H, B = 4, 3
+    for (c1, c2) in ((60, 96), (200, 80)):
+        lo1, hi1, lo2, hi2 = c1 - B - H, c1 + B + H, c2 - B - H, c2 + B + H
+        Ig = I4[:, lo1:hi1, lo2:hi2, :].double().cpu()
+        b1s = b1.reshape(n)[lo1:hi1, lo2:hi2]
+        b2s = b2.reshape(n)[lo1:hi1, lo2:hi2]
+        I0s = (a1[:, None, None, None] * b1s[None] + a2[:, None, None, None] * b2s[None]).astype(np.float64)
+        sub = dict(wl)
+        dx1 = (wl["xhi"][0] - wl["xlo"][0]) / n[0]
+        dx2 = (wl["xhi"][1] - wl["xlo"][1]) / n[1]
+        sub["n"] = (hi1 - lo1, hi2 - lo2, n[2])
+        sub["xlo"] = (wl["xlo"][0] + lo1 * dx1, wl["xlo"][1] + lo2 * dx2, wl["xlo"][2])
+        sub["xhi"] = (wl["xlo"][0] + hi1 * dx1, wl["xlo"][1] + hi2 * dx2, wl["xhi"][2])
+        for key in ("rho", "T", "I0_iso"):
+            sub[key] = wl[key][lo1:hi1, lo2:hi2]
+        sub["u"] = wl["u"][:, lo1:hi1, lo2:hi2]
+        sub["pole_rows"] = 0
+        sub["bc"] = ("outflow", "outflow", "periodic")
+        sub["bc_hi"] = ("outflow", "outflow", "periodic")
+        sub["dt"] = dt
+        _say(f"  sub-box r[{lo1}:{hi1}] theta[{lo2}:{hi2}]")
+        o = oracle_run(sub, 1, I0=I0s)
+        inner = (slice(H, -H), slice(H, -H))
+        Jg = torch.tensordot(torch.as_tensor(wgt), Ig, dims=1)[inner]
+        Jo = torch.tensordot(torch.as_tensor(wgt), o["I"], dims=1)[inner]
+        assert rel_l2(Jg, Jo) < 1e-5, rel_l2(Jg, Jo)
+        assert rel_l2(Ig[:, H:-H, H:-H], o["I"][:, H:-H, H:-H]) < 1e-5
+        assert rel_l2(Tg[lo1:hi1, lo2:hi2][inner], o["T"][inner]) < 1e-5
+    ctx.close()
+
+
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_ks_generation3(precision):
     """642 directions: the angular kernel keeps only the intensities in LDS
