@@ -31,19 +31,15 @@ namespace {
 // CW threads; a thread keeps one cell (t % CW) throughout and its group takes
 // every (256 / CW)-th direction, so a load's address advances by a uniform
 // stride and the LDS slots by immediate offsets.
-// LCO: the position's coefficient rows and the neighbour lists are staged in
-// LDS too (few directions); without it (many directions, e.g. 642) the LDS
-// holds only the intensities, so that the run stays long, and the rows and
-// lists are read from memory, where every group of the workgroup shares them.
-template <typename S, int CW, bool LCO>
+template <typename S, int CW>
 __global__ void __launch_bounds__(256)
 k_angular(long long nc, int n3, int ns, const S* __restrict__ I, S* __restrict__ D,
           const S* __restrict__ coef, const int* __restrict__ nbr) {
   constexpr int NGRP = 256 / CW;
   extern __shared__ unsigned char smem_raw[];
-  // LDS: the run's intensities [ns][CW] and, with LCO, its coefficient rows
-  // [ns][KS_ROW] and the neighbour lists [ns][KS_ROW] as byte offsets of the
-  // neighbours' rows in the intensity block (16 bits: ns CW elem < 64 KiB)
+  // LDS: the run's intensities [ns][CW], its coefficient rows [ns][KS_ROW]
+  // and the neighbour lists [ns][KS_ROW] as byte offsets of the neighbours'
+  // rows in the intensity block (16 bits: ns CW elem < 64 KiB)
   S* col = reinterpret_cast<S*>(smem_raw);
   S* lco = col + ns * CW;
   unsigned short* lnb = reinterpret_cast<unsigned short*>(lco + ns * KS_ROW);
@@ -60,11 +56,10 @@ k_angular(long long nc, int n3, int ns, const S* __restrict__ I, S* __restrict__
   // the coefficient rows and neighbour lists go to LDS first; their reads
   // overlap those of the intensities
   const S* A = coef + row * (long long)ns * KS_ROW;
-  if (LCO)
-    for (int k = t; k < ns * KS_ROW; k += 256) {
-      lco[k] = A[k];
-      lnb[k] = (unsigned short)(nbr[k] * CW * (int)sizeof(S));
-    }
+  for (int k = t; k < ns * KS_ROW; k += 256) {
+    lco[k] = A[k];
+    lnb[k] = (unsigned short)(nbr[k] * CW * (int)sizeof(S));
+  }
   // this thread's cell in every direction of its group (cells past the run
   // re-read the run's last cell and stage zeros)
   const S* src = I + (long long)grp * nc + cbase + min(l, ncol - 1);
@@ -86,22 +81,71 @@ k_angular(long long nc, int n3, int ns, const S* __restrict__ I, S* __restrict__
   S* dst = D + (long long)grp * nc + cbase + l;
 #pragma unroll 2
   for (int s = grp; s < ns; s += NGRP) {
-    S acc;
-    if (LCO) {
-      const S* a = lco + s * KS_ROW;
-      const unsigned short* o = lnb + s * KS_ROW;
-      acc = a[0] * col[s * CW + l];
+    const S* a = lco + s * KS_ROW;
+    const unsigned short* o = lnb + s * KS_ROW;
+    S acc = a[0] * col[s * CW + l];
 #pragma unroll
-      for (int j = 1; j <= KS_DEG; ++j) acc += a[j] * *reinterpret_cast<const S*>(lane + o[j]);
-    } else {
-      const S* a = A + s * KS_ROW;
-      const int* o = nbr + s * KS_ROW;
-      acc = a[0] * col[s * CW + l];
-#pragma unroll
-      for (int j = 1; j <= KS_DEG; ++j) acc += a[j] * col[o[j] * CW + l];
-    }
+    for (int j = 1; j <= KS_DEG; ++j) acc += a[j] * *reinterpret_cast<const S*>(lane + o[j]);
     if (inrun) *dst = acc;
     dst += stride;
+  }
+}
+
+// The same divergence for many directions (all of a cell's directions no
+// longer fit LDS beside a useful run): workgroup (patch p, position, run of CW
+// cells) stages the rows of its load list -- the patch's own directions, then
+// the neighbours outside it -- and forms D' for the patch's own directions.
+// lnb holds, per direction, the positions of its row set (itself, then its
+// padded neighbours) in its patch's list.  With CW elem = 256 bytes the rows
+// move in 256-byte pieces.
+template <typename S, int CW>
+__global__ void __launch_bounds__(256)
+k_angular_patch(long long nc, int n3, int ns, long long nruns, const S* __restrict__ I,
+                S* __restrict__ D, const S* __restrict__ coef, const int* __restrict__ plist,
+                const int* __restrict__ poff, const int* __restrict__ pnout,
+                const int* __restrict__ lnb) {
+  constexpr int NGRP = 256 / CW;
+  __shared__ S col[KS_PATCH_LOADS][CW];
+  // the patch is the slowest index: consecutive workgroups read the same rows
+  // at neighbouring cells
+  const int p = (int)(blockIdx.x / nruns);
+  const long long run = blockIdx.x % nruns;
+  const int chunks = (n3 + CW - 1) / CW;
+  const long long row = run / chunks;  // (i1, i2) position
+  const int x0 = (int)(run % chunks) * CW;
+  const long long cbase = row * n3 + x0;
+  const int t = threadIdx.x;
+  const int ncol = min(CW, n3 - x0);
+  const int l = t % CW;
+  int grp = t / CW;
+  if (CW == 64) grp = __builtin_amdgcn_readfirstlane(grp);
+  const bool inrun = l < ncol;
+  const int* list = plist + poff[p];
+  const int nl = poff[p + 1] - poff[p], nout = pnout[p];
+  const long long cell = cbase + min(l, ncol - 1);
+  constexpr int B = 16;
+  for (int u0 = grp; u0 < nl; u0 += B * NGRP) {
+    S v[B];
+#pragma unroll
+    for (int u = 0; u < B; ++u) {
+      const int li = min(u0 + u * NGRP, nl - 1);
+      v[u] = I[(long long)list[li] * nc + cell];
+    }
+#pragma unroll
+    for (int u = 0; u < B; ++u)
+      if (u0 + u * NGRP < nl) col[u0 + u * NGRP][l] = inrun ? v[u] : S(0);
+  }
+  __syncthreads();
+  const S* A = coef + row * (long long)ns * KS_ROW;
+#pragma unroll 2
+  for (int li = grp; li < nout; li += NGRP) {
+    const int s = list[li];
+    const S* a = A + s * KS_ROW;
+    const int* o = lnb + s * KS_ROW;
+    S acc = a[0] * col[li][l];
+#pragma unroll
+    for (int j = 1; j <= KS_DEG; ++j) acc += a[j] * col[o[j]][l];
+    if (inrun) D[(long long)s * nc + cbase + l] = acc;
   }
 }
 
@@ -110,18 +154,20 @@ hipError_t launch_cw(rt_ctx* c, const void* I, hipStream_t st) {
   const long long nrt = (long long)c->n[0] * c->n[1];
   const int cw = c->ks_cw;
   const dim3 grid((unsigned)(nrt * ((c->n[2] + cw - 1) / cw))), block(256);
-  const bool lco = c->ks_lco;
-  const size_t lds = angular_lds_bytes(c->ns, cw, sizeof(S), lco);
   const S* in = (const S*)I;
   S* out = (S*)c->d_angD;
   const S* A = (const S*)c->d_acoef;
-#define RT_ANG(CW)                                                                                      \
-  if (lco)                                                                                              \
-    hipLaunchKernelGGL((k_angular<S, CW, true>), grid, block, lds, st, c->nc, c->n[2], c->ns, in, out, A, \
-                       c->d_inc);                                                                       \
-  else                                                                                                  \
-    hipLaunchKernelGGL((k_angular<S, CW, false>), grid, block, lds, st, c->nc, c->n[2], c->ns, in, out, A, \
-                       c->d_inc)
+  if (!c->ks_lco) {
+    constexpr int PCW = 256 / (int)sizeof(S);  // 256-byte rows
+    const long long nruns = nrt * ((c->n[2] + PCW - 1) / PCW);
+    const dim3 pgrid((unsigned)(nruns * c->ks_npatch));
+    hipLaunchKernelGGL((k_angular_patch<S, PCW>), pgrid, block, 0, st, c->nc, c->n[2], c->ns, nruns,
+                       in, out, A, c->d_plist, c->d_poff, c->d_pnout, c->d_plnb);
+    return hipGetLastError();
+  }
+  const size_t lds = angular_lds_bytes(c->ns, cw, sizeof(S), true);
+#define RT_ANG(CW) \
+  hipLaunchKernelGGL((k_angular<S, CW>), grid, block, lds, st, c->nc, c->n[2], c->ns, in, out, A, c->d_inc)
   switch (cw) {
     case 64: RT_ANG(64); break;
     case 32: RT_ANG(32); break;

@@ -130,18 +130,18 @@ rt_status set_kerr_schild(rt_ctx* c, double M, double a, double cfl) {
   }
   // angular kernel: runs of up to 32 phi cells with the coefficient rows in LDS
   // as long as the run's LDS stays within 40 KiB (four workgroups per compute
-  // unit) and the run keeps at least 16 cells; with more directions the LDS
-  // holds only the intensities of runs of up to 64 cells within 48 KiB
+  // unit) and the run keeps at least 16 cells.  With more directions the
+  // directions are split into patches (below) and a workgroup stages one
+  // patch's directions and their neighbours for a run of 256-byte rows.
   int cw = 32;
   bool lco = true;
   while (cw > 16 && angular_lds_bytes(c->ns, cw, c->elem, true) > 40960) cw /= 2;
   if (angular_lds_bytes(c->ns, cw, c->elem, true) > 40960) {
     lco = false;
-    cw = 64;
-    while (cw > 1 && angular_lds_bytes(c->ns, cw, c->elem, false) > 49152) cw /= 2;
+    cw = (int)(256 / c->elem);
   }
-  // (the kernel keeps 16-bit byte offsets into the run's intensity block)
-  if (angular_lds_bytes(c->ns, cw, c->elem, lco) > 65536 || (size_t)c->ns * cw * c->elem > 65535)
+  // (the LCO kernel keeps 16-bit byte offsets into the run's intensity block)
+  if (lco && (size_t)c->ns * cw * c->elem > 65535)
     return fail(RT_E_ARG, "rt_set_metric: too many directions for the curved form");
   c->ks_lco = lco;
   c->ks_cw = cw;
@@ -171,7 +171,61 @@ rt_status set_kerr_schild(rt_ctx* c, double M, double a, double cfl) {
       for (int j = 0; j < deg; ++j) D[1 + j] = A[ns + k0 + j];
     }
   }
+  // Patches (many directions): grow compact sets of directions over the
+  // neighbour graph, breadth first, while the set and its outside neighbours
+  // (the halo) fit the workgroup's LDS (KS_PATCH_LOADS rows); a patch's load
+  // list is its own directions, then the halo.  Per direction the kernel gets
+  // the local positions of itself and its padded neighbours in its patch's list.
+  std::vector<int> plist, poff(1, 0), pnout, lnb;
+  if (!lco) {
+    std::vector<int> owner(ns, -1);
+    lnb.assign((size_t)ns * KS_ROW, 0);
+    for (int seed = 0; seed < ns; ++seed) {
+      if (owner[seed] >= 0) continue;
+      const int p = (int)pnout.size();
+      std::vector<int> out, halo, queue(1, seed);
+      for (size_t qi = 0; qi < queue.size(); ++qi) {
+        const int v = queue[qi];
+        if (owner[v] >= 0) continue;
+        // halo after adding v: without v, with v's neighbours outside the patch
+        std::vector<int> h2;
+        for (int x : halo)
+          if (x != v) h2.push_back(x);
+        for (int j = 1; j <= KS_DEG; ++j) {
+          const int u = inc[(size_t)v * KS_ROW + j];
+          if (u == v || owner[u] == p || std::find(h2.begin(), h2.end(), u) != h2.end()) continue;
+          h2.push_back(u);
+        }
+        if ((int)(out.size() + 1 + h2.size()) > KS_PATCH_LOADS) continue;
+        owner[v] = p;
+        out.push_back(v);
+        halo.swap(h2);
+        for (int j = 1; j <= KS_DEG; ++j) {
+          const int u = inc[(size_t)v * KS_ROW + j];
+          if (owner[u] < 0) queue.push_back(u);
+        }
+      }
+      std::sort(halo.begin(), halo.end());
+      const int base = (int)plist.size();
+      plist.insert(plist.end(), out.begin(), out.end());
+      plist.insert(plist.end(), halo.begin(), halo.end());
+      poff.push_back((int)plist.size());
+      pnout.push_back((int)out.size());
+      for (size_t k = 0; k < out.size(); ++k) {
+        const int sd = out[k];
+        for (int j = 0; j < KS_ROW; ++j) {
+          const int u = inc[(size_t)sd * KS_ROW + j];
+          const auto it = std::find(plist.begin() + base, plist.end(), u);
+          lnb[(size_t)sd * KS_ROW + j] = (int)(it - (plist.begin() + base));
+        }
+      }
+    }
+  }
+  c->ks_npatch = (int)pnout.size();
   rt_status st = RT_OK;
+  if (!lco && ((st = upload(&c->d_plist, plist)) || (st = upload(&c->d_poff, poff)) ||
+               (st = upload(&c->d_pnout, pnout)) || (st = upload(&c->d_plnb, lnb))))
+    return st;
   if ((st = upload_as(c, &c->d_rec_r, T.fr)) || (st = upload_as(c, &c->d_rec_t, T.ft)) ||
       (st = upload_as(c, &c->d_rec_p, T.fp)) || (st = upload_as(c, &c->d_acoef, coef8)) ||
       (st = upload(&c->d_zin, T.zin)) ||
@@ -635,6 +689,10 @@ void rt_destroy(rt_ctx* c) {
   release(c->d_e);
   release(c->d_einv);
   release(c->d_inc);
+  release(c->d_plist);
+  release(c->d_poff);
+  release(c->d_pnout);
+  release(c->d_plnb);
   release(c->d_angD);
   for (auto& t : c->timed) {
     (void)hipEventDestroy(t.a);

@@ -37,6 +37,12 @@ struct rt_ctx {
   double* d_e = nullptr;         // [N1 N2][16] e^mu_a
   double* d_einv = nullptr;      // [N1 N2][16] e^a_mu
   int* d_inc = nullptr;          // [ns][KS_ROW] the direction, then its neighbours (padded)
+  // patches of directions for the angular kernel with many directions
+  int ks_npatch = 0;
+  int* d_plist = nullptr;        // load lists, concatenated: the patch's directions, then its halo
+  int* d_poff = nullptr;         // [npatch + 1] offsets into d_plist
+  int* d_pnout = nullptr;        // [npatch] directions owned by the patch (the list's head)
+  int* d_plnb = nullptr;         // [ns][KS_ROW] positions of a direction's row set in its patch's list
   void* d_angD = nullptr;        // [ns][nc] angular divergence scratch
 
   // device grid tables
@@ -88,6 +94,9 @@ namespace rt {
 // angular coupling of the curved geometry: a direction of the geodesic grid
 // has at most KS_DEG neighbours; its coefficient row holds KS_ROW entries
 constexpr int KS_DEG = 6, KS_ROW = 8;
+// rows (directions) one workgroup of the patched angular kernel stages: 48 KiB
+// of 256-byte rows
+constexpr int KS_PATCH_LOADS = 192;
 // LDS of the angular kernel for a run of cw cells: intensities and, when lco,
 // the coefficient rows and 16-bit neighbour lists
 inline size_t angular_lds_bytes(int ns, int cw, size_t elem, bool lco) {
