@@ -235,6 +235,21 @@ def test_ks_c5_full_size_fp32_sampled():
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_ks_generation4_patches(precision):
+    """2562 directions: the angular kernel runs on 19 patches of directions
+    with halos of 42-79 rows (several partly filled); 4 x 6 x 70 cells, so the
+    256-byte rows of a phi run end in a ragged one."""
+    wl, I0 = _case(n=(4, 6, 70), generation=4, pole_rows=1)
+    _say(f"torus_ks {precision} g4 4x6x70 1 step")
+    g = gpu_run(wl, 1, precision=precision, I0=I0)
+    o = oracle_run(wl, 1, I0=I0)
+    if precision == "fp64":
+        _check_fp64(g, o, wl)
+    else:
+        _check_fp32(g, o)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_ks_generation3(precision):
     """642 directions: the angular kernel keeps only the intensities in LDS
     (runs of 8 phi cells in FP64, 16 in FP32) and reads the coefficient rows
