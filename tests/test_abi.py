@@ -75,6 +75,8 @@ def _desc(N, **kw):
     (dict(coords=1, pole_zero_rows=3), b"pole_zero_rows"),
     (dict(coords=0, pole_zero_rows=1), b"pole_zero_rows"),
     (dict(n0_cut=-1.0), b"n0_cut"),
+    # one direction's plane must stay below 4 GiB (32-bit byte offsets in the stage kernels)
+    (dict(n=(1024, 1024, 512)), b"2^29"),
 ])
 def test_bad_descriptors_are_rejected(kw, msg):
     N, lib = _lib()
