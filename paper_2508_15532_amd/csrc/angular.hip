@@ -105,7 +105,13 @@ k_angular_patch(long long nc, int n3, int ns, long long nruns, const S* __restri
                 const int* __restrict__ poff, const int* __restrict__ pnout,
                 const int* __restrict__ lnb) {
   constexpr int NGRP = 256 / CW;
+  // LDS: the rows of the load list; for the patch's own directions their
+  // direction number, coefficient row and local row-set positions (so that
+  // the sum below reads LDS only)
   __shared__ S col[KS_PATCH_LOADS][CW];
+  __shared__ S lco[KS_PATCH_LOADS][KS_ROW];
+  __shared__ unsigned short lnl[KS_PATCH_LOADS][KS_ROW];
+  __shared__ int ldir[KS_PATCH_LOADS];
   // the patch is the slowest index: consecutive workgroups read the same rows
   // at neighbouring cells
   const int p = (int)(blockIdx.x / nruns);
@@ -122,6 +128,14 @@ k_angular_patch(long long nc, int n3, int ns, long long nruns, const S* __restri
   const bool inrun = l < ncol;
   const int* list = plist + poff[p];
   const int nl = poff[p + 1] - poff[p], nout = pnout[p];
+  const S* A = coef + row * (long long)ns * KS_ROW;
+  for (int k = t; k < nout * KS_ROW; k += 256) {
+    const int li = k / KS_ROW, j = k % KS_ROW;
+    const int s = list[li];
+    lco[li][j] = A[s * KS_ROW + j];
+    lnl[li][j] = (unsigned short)lnb[s * KS_ROW + j];
+    if (j == 0) ldir[li] = s;
+  }
   const long long cell = cbase + min(l, ncol - 1);
   constexpr int B = 16;
   for (int u0 = grp; u0 < nl; u0 += B * NGRP) {
@@ -136,16 +150,14 @@ k_angular_patch(long long nc, int n3, int ns, long long nruns, const S* __restri
       if (u0 + u * NGRP < nl) col[u0 + u * NGRP][l] = inrun ? v[u] : S(0);
   }
   __syncthreads();
-  const S* A = coef + row * (long long)ns * KS_ROW;
 #pragma unroll 2
   for (int li = grp; li < nout; li += NGRP) {
-    const int s = list[li];
-    const S* a = A + s * KS_ROW;
-    const int* o = lnb + s * KS_ROW;
+    const S* a = lco[li];
+    const unsigned short* o = lnl[li];
     S acc = a[0] * col[li][l];
 #pragma unroll
     for (int j = 1; j <= KS_DEG; ++j) acc += a[j] * col[o[j]][l];
-    if (inrun) D[(long long)s * nc + cbase + l] = acc;
+    if (inrun) D[(long long)ldir[li] * nc + cbase + l] = acc;
   }
 }
 

@@ -94,9 +94,10 @@ namespace rt {
 // angular coupling of the curved geometry: a direction of the geodesic grid
 // has at most KS_DEG neighbours; its coefficient row holds KS_ROW entries
 constexpr int KS_DEG = 6, KS_ROW = 8;
-// rows (directions) one workgroup of the patched angular kernel stages: 48 KiB
-// of 256-byte rows
-constexpr int KS_PATCH_LOADS = 192;
+// rows (directions) one workgroup of the patched angular kernel stages: 40 KiB
+// of 256-byte rows, plus the patch's coefficient rows (three workgroups per
+// compute unit)
+constexpr int KS_PATCH_LOADS = 160;
 // LDS of the angular kernel for a run of cw cells: intensities and, when lco,
 // the coefficient rows and 16-bit neighbour lists
 inline size_t angular_lds_bytes(int ns, int cw, size_t elem, bool lco) {
