@@ -23,6 +23,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X published HBM3E bandwidth
+MFMA_F64_PEAK_TFS = 78.6       # MI355X published dense FP64 matrix-core rate
 CSRC = os.path.join(ROOT, "paper_2508_15532_amd", "csrc")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 
@@ -155,6 +156,34 @@ def cpu_baseline(torch):
                       f"box drawn with the 128^3 workload's recipe ({dt:.1f} s)"}
 
 
+def run_moments(wl, precision, launches, warmup, torch, P):
+    """Time rt_moments (R^(ab) of a whole intensity field: the [cells x dirs] x
+    [dirs x 10] FP64 contraction on MFMA) on the workload's initial field."""
+    ctx, _ = make_context(wl, precision, P)
+    keep, I, T, R = make_inputs(wl, ctx, torch)
+    for _ in range(warmup):
+        ctx.moments(I, R)
+    torch.cuda.synchronize()
+    ctx.set_debug(2)
+    ctx.kernel_times()
+    for _ in range(launches):
+        ctx.moments(I, R)
+    torch.cuda.synchronize()
+    n, ms = ctx.kernel_times()["moments"]
+    ctx.set_debug(0)
+    ns, nc = ctx.ns, ctx.nc
+    elem = 4 if precision == "fp32" else 8
+    ctx.close()
+    del I, T, R, keep
+    torch.cuda.empty_cache()
+    avg_s = ms / max(n, 1) / 1e3
+    gbs = algorithmic_bytes("moments", elem, ns, nc) / avg_s / 1e9
+    tflops = 2.0 * nc * ns * 10 / avg_s / 1e12
+    return {"intensity": precision, "launches": n, "avg_ms": avg_s * 1e3,
+            "achieved_GBs": gbs, "hbm_frac": gbs / HBM_PEAK_GBS,
+            "mfma_f64_TFLOPs": tflops, "mfma_frac": tflops / MFMA_F64_PEAK_TFS}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -168,6 +197,8 @@ def main():
                     help="skip the Kerr-Schild torus line (256x128x64 x 162, FP32)")
     ap.add_argument("--no-big-torus", action="store_true",
                     help="skip the large turbulent-torus line (384x192x128 x 642, FP32, 3 steps)")
+    ap.add_argument("--moments-only", action="store_true",
+                    help="only time rt_moments on the 128^3 x 162 field (FP32 and FP64) and print it")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy 5 times (the "
                          "reference kernel for scaling HBM byte counters) and exit")
@@ -194,6 +225,9 @@ def main():
         sys.exit(1)
     wl = W.brems_flat()
     forms = args.forms.split(",")
+    if args.moments_only:
+        print(json.dumps({"moments": [run_moments(wl, prec, 10, 2, torch, P) for prec in forms]}))
+        return
     res = {}
     for prec in forms:
         print(f"bench: {prec} 128^3 x 162, {args.warmup} warmup + {args.steps} timed steps",
@@ -284,6 +318,10 @@ def main():
                 "finite": br["finite"]}
         except Exception as e:  # reported in the line, the headline stands
             out["torus_ks_384x192x128_g3"] = {"error": f"{type(e).__name__}: {e}"}
+    # the standalone moment contraction (inside rt_step R is formed in the
+    # materialisation pass instead)
+    print("bench: rt_moments 128^3 x 162", file=sys.stderr, flush=True)
+    out["moments"] = [run_moments(wl, prec, 10, 2, torch, P) for prec in forms]
     if not args.no_cpu_baseline:
         print("bench: CPU oracle baseline", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(torch)

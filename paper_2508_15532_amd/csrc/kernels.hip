@@ -38,13 +38,38 @@ k_moments(long long nc, int ns, const S* __restrict__ I, const double* __restric
   const int r = lane & 15, kq = lane >> 4;
   d4 acc[4];
   for (int m = 0; m < 4; ++m) acc[m] = d4{0.0, 0.0, 0.0, 0.0};
-  for (int s0 = 0; s0 < ns; s0 += 4) {
-    const int s = s0 + kq;
-    const double b = W16[s * 16 + r];  // W16 is zero-padded to a multiple of 4 rows
-    for (int m = 0; m < 4; ++m) {
-      long long cc = cell0 + 16 * m + r;
-      double av = (s < ns && cc < nc) ? (double)I[(long long)s * nc + cc] : 0.0;
-      acc[m] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, b, acc[m], 0, 0, 0);
+  if constexpr (sizeof(S) == 4) {
+    for (int s0 = 0; s0 < ns; s0 += 4) {
+      const int s = s0 + kq;
+      const double b = W16[s * 16 + r];  // W16 is zero-padded to a multiple of 4 rows
+      for (int m = 0; m < 4; ++m) {
+        long long cc = cell0 + 16 * m + r;
+        double av = (s < ns && cc < nc) ? (double)I[(long long)s * nc + cc] : 0.0;
+        acc[m] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, b, acc[m], 0, 0, 0);
+      }
+    }
+  } else {
+    // FP64 intensities: batches of B four-direction steps, all loads of a batch
+    // issued before its matrix products (4 B loads per lane in flight); with
+    // FP32 ones the plain loop, with more resident waves, is faster (measured)
+    constexpr int B = 4;
+    for (int s00 = 0; s00 < ns; s00 += 4 * B) {
+      double av[B][4], b[B];
+#pragma unroll
+      for (int u = 0; u < B; ++u) {
+        const int s = s00 + 4 * u + kq;
+        b[u] = s < ns ? W16[s * 16 + r] : 0.0;
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+          const long long cc = cell0 + 16 * m + r;
+          av[u][m] = (s < ns && cc < nc) ? (double)I[(long long)s * nc + cc] : 0.0;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < B; ++u)
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+          acc[m] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u][m], b[u], acc[m], 0, 0, 0);
     }
   }
   for (int m = 0; m < 4; ++m) {
