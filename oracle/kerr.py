@@ -19,7 +19,8 @@ parameter with dx/dlambda = n^mu, at the rate
 which follows from the geodesic equation in the tetrad basis (this fixes the
 sign that the printed r^zeta leaves ambiguous).  The angular flux across a
 geodesic edge with outward unit normal u_e at midpoint m_e (Sec. 3.5,
-Eq. angular_fluxes, donor-cell states) is F_e = n_0(m_e) (r(m_e) . u_e) I_upwind.
+Eq. angular_fluxes) is F_e = n_0(m_e) (r(m_e) . u_e) I_upwind, with donor-cell
+or MAPR (oracle.mapr) upwind states.
 
 Kerr-Schild metric (units G = c = M = 1 scaled by M), Sigma = r^2 + a^2 cos^2 th,
 z = 2 M r / Sigma:
@@ -136,7 +137,10 @@ class KerrSchildLogR:
 
     kind = "kerr_schild"
 
-    def __init__(self, n, xlo, xhi, grid, a, M=1.0, fd_h=1e-3):
+    def __init__(self, n, xlo, xhi, grid, a, M=1.0, fd_h=1e-3, recon="donor"):
+        if recon not in ("donor", "mapr"):
+            raise ValueError(recon)
+        self.recon = recon
         self.n = tuple(int(v) for v in n)
         self.xlo, self.xhi = tuple(map(float, xlo)), tuple(map(float, xhi))
         self.dx = tuple((b - c) / m for c, b, m in zip(self.xlo, self.xhi, self.n))
@@ -246,12 +250,21 @@ class KerrSchildLogR:
         return cfl * best
 
     def angular(self, I):
-        """(1/w_s) sum_e dlambda_e F_e for every direction and cell, donor-cell states."""
+        """(1/w_s) sum_e dlambda_e F_e for every direction and cell; the edge
+        states are the upwind direction's own intensity (donor cell) or its
+        MAPR reconstruction at the edge midpoint (oracle.mapr)."""
         g = self.grid
         es, et = torch.as_tensor(g.edges[:, 0]), torch.as_tensor(g.edges[:, 1])
         v = self._t(self.v_edge, (-1, self.n[0], self.n[1], 1))
         n0 = self._t(self.n0_edge, (-1, self.n[0], self.n[1], 1))
-        Iup = torch.where(v > 0, I[es], I[et])
+        if self.recon == "mapr":
+            from . import mapr
+            if not hasattr(self, "_ring"):
+                self._ring = mapr.rings(g)
+            first, second = mapr.edge_states(g, I, self._ring)
+            Iup = torch.where(v > 0, first, second)
+        else:
+            Iup = torch.where(v > 0, I[es], I[et])
         F = n0 * v * Iup * torch.as_tensor(g.dlam, dtype=F64).reshape(-1, 1, 1, 1)
         w = torch.as_tensor(g.w, dtype=F64).reshape(-1, 1, 1, 1)
         div = torch.zeros_like(I)

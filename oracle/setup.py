@@ -48,7 +48,8 @@ def build_ks(wl, grid=None, limiter=tr.LIM_MC, fd_h=1e-3):
     """Problem on the Kerr-Schild (ln r, theta, phi) mesh; returns (pb, I0, T0, dt_max)."""
     from .kerr import KerrSchildLogR
     grid = grid or GeodesicGrid(wl["generation"], wl["weights"])
-    geo = KerrSchildLogR(wl["n"], wl["xlo"], wl["xhi"], grid, wl["a"], wl.get("M", 1.0), fd_h)
+    geo = KerrSchildLogR(wl["n"], wl["xlo"], wl["xhi"], grid, wl["a"], wl.get("M", 1.0), fd_h,
+                         recon=wl.get("angular_recon", "donor"))
     shape = tuple(wl["n"])
     u = np.asarray(wl["u"], dtype=np.float64)
     u_hat = geo.u_hat(u)
