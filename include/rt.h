@@ -63,6 +63,12 @@ enum { RT_W_VORONOI = 0, RT_W_EQUAL = 1 };
 enum { RT_FP64 = 0, RT_FP32_TRANSPORT = 1 };
 /* PLI slope limiter (Sec. 3.4) */
 enum { RT_LIM_MC = 0, RT_LIM_MINMOD = 1 };
+/* states at the Voronoi edges for the angular fluxes of the curved geometry
+   (Sec. 3.5): the upwind direction's own intensity (donor cell), or its MAPR
+   reconstruction: the flattest of the planes through the direction and
+   consecutive pairs of its neighbours in gnomonic coordinates, evaluated at
+   the edge midpoint and replaced by the cell value where negative */
+enum { RT_AREC_DONOR = 0, RT_AREC_MAPR = 1 };
 /* metric (fixed in time, Sec. 2.1.1) */
 enum { RT_FLAT = 0, RT_KERR_SCHILD = 1 };
 /* opacity / emission model (Sec. 3.6.2):
@@ -87,7 +93,7 @@ typedef struct {
   int weights;         /* RT_W_VORONOI or RT_W_EQUAL (4 pi / Ns) */
   int precision;       /* RT_FP64 or RT_FP32_TRANSPORT */
   int limiter;         /* RT_LIM_MC or RT_LIM_MINMOD */
-  int angular_recon;   /* reserved (0): donor-cell angular states */
+  int angular_recon;   /* RT_AREC_DONOR or RT_AREC_MAPR (curved geometry only) */
   double abar;         /* coefficient in tau = abar alpha-hat dt (Sec. 3.5); 1 */
   double rho_floor;    /* no interaction below this density (Sec. 3.8); 5e-4 */
   double n0_cut;       /* |n_0| below which I is zeroed (Sec. 3.5, curved only); 0.1 */

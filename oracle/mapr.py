@@ -13,8 +13,12 @@ The paper names the method without spelling it out.  Reading used here:
     (p_b, I_b): the tangent slope vector g in span(p_a, p_b) with
     g . p_a = I_a - I_s and g . p_b = I_b - I_s;
   * of these planes the one with the smallest slope |g| (the smallest angle
-    with the tangent plane) is taken; an exact tie keeps the first pair in the
-    cyclic order starting from the neighbour at the smallest angle;
+    with the tangent plane) is taken.  Ties are common (a symmetric
+    neighbourhood with equal or zeroed intensities gives congruent planes of
+    equal slope) and rounding must not decide them: every plane whose |g|^2 is
+    within a relative TIE_RTOL of the smallest counts as minimal, and the first
+    of them is taken, in counter-clockwise order (seen from outside the sphere)
+    starting at the neighbour with the smallest direction index;
   * the state of s at a point m of its Voronoi cell is I_s + g . p_s(m),
     replaced by I_s where that is negative.
 The angular flux across an edge takes the state of its upwind direction at the
@@ -27,6 +31,7 @@ import numpy as np
 import torch
 
 F64 = torch.float64
+TIE_RTOL = 1e-8     # relative |g|^2 band of the minimal planes (FP64)
 
 
 def gnomonic(n_s, x):
@@ -37,7 +42,7 @@ def gnomonic(n_s, x):
 
 def rings(grid):
     """For every direction, its neighbours in counter-clockwise order seen from
-    outside the sphere, starting at an arbitrary neighbour."""
+    outside the sphere, starting at the neighbour with the smallest index."""
     nb = [[] for _ in range(grid.ns)]
     for a, b in grid.edges:
         nb[a].append(int(b))
@@ -49,7 +54,9 @@ def rings(grid):
         ref = P[0] / np.linalg.norm(P[0])
         perp = np.cross(n, ref)
         ang = np.arctan2(P @ perp, P @ ref)
-        out.append([nb[s][k] for k in np.argsort(ang, kind="stable")])
+        r = [nb[s][k] for k in np.argsort(ang, kind="stable")]
+        k0 = r.index(min(r))
+        out.append(r[k0:] + r[:k0])
     return out
 
 
@@ -73,18 +80,15 @@ def slopes(grid, I, ring=None):
         n = grid.n[s]
         r = ring[s]
         P = gnomonic(n, grid.n[r])
-        best, bn = None, None
+        cand = []
         for k in range(len(r)):
             a, b = k, (k + 1) % len(r)
-            g = pair_slope(P[a], P[b], I[r[a]] - I[s], I[r[b]] - I[s])
-            nrm = (g * g).sum(-1)
-            if best is None:
-                best, bn = g, nrm
-            else:
-                take = nrm < bn
-                best = torch.where(take[..., None], g, best)
-                bn = torch.where(take, nrm, bn)
-        out[s] = best
+            cand.append(pair_slope(P[a], P[b], I[r[a]] - I[s], I[r[b]] - I[s]))
+        cand = torch.stack(cand)                               # [deg, *cells, 3]
+        norms = (cand * cand).sum(-1)                          # [deg, *cells]
+        minimal = norms <= norms.min(0).values * (1.0 + TIE_RTOL)
+        first = minimal.to(torch.int64).argmax(0)              # first minimal plane
+        out[s] = torch.gather(cand, 0, first[None, ..., None].expand((1,) + cand.shape[1:]))[0]
     return out
 
 

@@ -61,7 +61,7 @@ class RTContext:
 
     def __init__(self, n, xlo, xhi, generation, *, weights="voronoi", precision="fp64",
                  bc=("periodic",) * 3, bc_hi=None, limiter="mc", abar=1.0, rho_floor=5e-4,
-                 n0_cut=0.1, coords="cart", pole_zero_rows=None):
+                 n0_cut=0.1, coords="cart", pole_zero_rows=None, angular_recon="donor"):
         self._lib = N.load()
         d = N.GridDesc()
         bc_hi = bc if bc_hi is None else bc_hi
@@ -76,6 +76,7 @@ class RTContext:
         d.weights = {"voronoi": N.RT_W_VORONOI, "equal": N.RT_W_EQUAL}[weights]
         d.precision = _PREC[precision]
         d.limiter = {"mc": N.RT_LIM_MC, "minmod": N.RT_LIM_MINMOD}[limiter]
+        d.angular_recon = {"donor": N.RT_AREC_DONOR, "mapr": N.RT_AREC_MAPR}[angular_recon]
         d.abar, d.rho_floor, d.n0_cut = float(abar), float(rho_floor), float(n0_cut)
         if pole_zero_rows is None:
             pole_zero_rows = 4 if coords == "logr_theta_phi" else 0

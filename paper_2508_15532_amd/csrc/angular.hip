@@ -1,5 +1,5 @@
 // Angular flux divergence of the curved geometry (Sec. 3.5, geodesic-edge
-// fluxes; donor-cell states).
+// fluxes; donor-cell states, or MAPR states in the two kernels at the end).
 //
 // In a curved metric a photon's tetrad direction turns along its ray, so the
 // intensity also flows between neighbouring directions of the geodesic grid
@@ -193,9 +193,107 @@ hipError_t launch_cw(rt_ctx* c, const void* I, hipStream_t st) {
   return hipGetLastError();
 }
 
+// MAPR edge states (Sec. 3.5).  Pass 1: per direction s and cell, the slope of
+// the flattest plane through (0, I_s) and a consecutive pair (a, b) of the
+// neighbours in the gnomonic coordinates of s:
+//   g = Minv_(s,ab) (I_a - I_s, I_b - I_s).
+// Planes of equal slope are frequent (symmetric neighbourhoods with equal or
+// zeroed intensities), so rounding must not choose among them: every plane with
+// |g|^2 within the relative band tie_band<S>() of the smallest counts as
+// minimal and the first of them in the cyclic order is taken.  One thread per
+// cell, one direction per blockIdx.y, so the pair tables are uniform (scalar)
+// loads.
+template <typename S>
+__device__ constexpr S tie_band() { return sizeof(S) == 8 ? S(1e-8) : S(1e-4); }
+
+template <typename S>
+__global__ void __launch_bounds__(256)
+k_mapr_slope(long long nc, const S* __restrict__ I, S* __restrict__ G, const int* __restrict__ pair,
+             const S* __restrict__ minv) {
+  const long long c = (long long)blockIdx.x * 256 + threadIdx.x;
+  const int s = blockIdx.y;
+  if (c >= nc) return;
+  const S Is = I[(long long)s * nc + c];
+  const int* pr = pair + s * KS_DEG * 2;
+  const S* m = minv + s * KS_DEG * 4;
+  S h0[KS_DEG], h1[KS_DEG], nn[KS_DEG];
+  S lo = 0;
+#pragma unroll
+  for (int i = 0; i < KS_DEG; ++i) {
+    const S dA = I[(long long)pr[2 * i] * nc + c] - Is;
+    const S dB = I[(long long)pr[2 * i + 1] * nc + c] - Is;
+    h0[i] = m[4 * i] * dA + m[4 * i + 1] * dB;
+    h1[i] = m[4 * i + 2] * dA + m[4 * i + 3] * dB;
+    nn[i] = h0[i] * h0[i] + h1[i] * h1[i];
+    lo = i == 0 ? nn[i] : (nn[i] < lo ? nn[i] : lo);
+  }
+  const S thr = lo * (S(1) + tie_band<S>());
+  S g0 = h0[0], g1 = h1[0];
+#pragma unroll
+  for (int i = KS_DEG - 1; i >= 0; --i)
+    if (nn[i] <= thr) {
+      g0 = h0[i];
+      g1 = h1[i];
+    }
+  G[2LL * s * nc + c] = g0;
+  G[(2LL * s + 1) * nc + c] = g1;
+}
+
+// Pass 2: D'_s = sum_j a_sj R_j over the neighbour slots j of s, with R_j the
+// state at the edge midpoint of the slot's upwind side: I_u + g_u . p_u(m),
+// I_u where that is negative (u = s or its neighbour, by the slot's flag).
+template <typename S>
+__global__ void __launch_bounds__(256)
+k_mapr_flux(long long nc, int n3, const S* __restrict__ I, const S* __restrict__ G, S* __restrict__ D,
+            const int* __restrict__ nbr, const S* __restrict__ pq, const S* __restrict__ coef,
+            const unsigned char* __restrict__ self) {
+  const long long c = (long long)blockIdx.x * 256 + threadIdx.x;
+  const int s = blockIdx.y, ns = gridDim.y;
+  if (c >= nc) return;
+  const long long q = c / n3;  // (i1, i2) position
+  const S* a = coef + (q * ns + s) * KS_ROW;
+  const unsigned f = self[q * ns + s];
+  const int* o = nbr + s * KS_ROW;
+  const S* w = pq + s * KS_ROW * 4;
+  const S Is = I[(long long)s * nc + c];
+  const S gs0 = G[2LL * s * nc + c], gs1 = G[(2LL * s + 1) * nc + c];
+  S acc = 0;
+#pragma unroll
+  for (int j = 1; j <= KS_DEG; ++j) {
+    S r;
+    if ((f >> j) & 1u) {
+      r = Is + gs0 * w[4 * j] + gs1 * w[4 * j + 1];
+      if (r < S(0)) r = Is;
+    } else {
+      const long long u = o[j];
+      const S Iu = I[u * nc + c];
+      r = Iu + G[2 * u * nc + c] * w[4 * j + 2] + G[(2 * u + 1) * nc + c] * w[4 * j + 3];
+      if (r < S(0)) r = Iu;
+    }
+    acc += a[j] * r;
+  }
+  D[(long long)s * nc + c] = acc;
+}
+
+template <typename S>
+hipError_t launch_mapr(rt_ctx* c, const void* I, hipStream_t st) {
+  const dim3 grid((unsigned)((c->nc + 255) / 256), (unsigned)c->ns), block(256);
+  const S* in = (const S*)I;
+  S* G = (S*)c->d_mp_grad;
+  hipLaunchKernelGGL((k_mapr_slope<S>), grid, block, 0, st, c->nc, in, G, c->d_mp_pair,
+                     (const S*)c->d_mp_minv);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_mapr_flux<S>), grid, block, 0, st, c->nc, c->n[2], in, (const S*)G,
+                     (S*)c->d_angD, c->d_inc, (const S*)c->d_mp_pq, (const S*)c->d_mp_coef,
+                     c->d_mp_self);
+  return hipGetLastError();
+}
+
 }  // namespace
 
 hipError_t launch_angular(rt_ctx* c, const void* I, hipStream_t st) {
+  if (c->mapr) return c->fp32 ? launch_mapr<float>(c, I, st) : launch_mapr<double>(c, I, st);
   return c->fp32 ? launch_cw<float>(c, I, st) : launch_cw<double>(c, I, st);
 }
 

@@ -119,6 +119,121 @@ rt_status upload(T** dst, const std::vector<T>& v) {
   return RT_OK;
 }
 
+// MAPR tables (Sec. 3.5, angular edge states).  Per direction s, with an
+// orthonormal basis (e1, e2) of its tangent plane, a point x has the gnomonic
+// coordinates of p = x / (x . n_s) - n_s.  The neighbours of s, sorted by the
+// angle of their coordinates (counter-clockwise seen from outside, from the
+// neighbour with the smallest index), give the consecutive pairs (a, b); the slope of
+// the plane through (0, I_s), (p_a, I_a), (p_b, I_b) is
+// g = [p_a; p_b]^-1 (I_a - I_s, I_b - I_s), and the kernels keep the inverse.
+// Pentagons repeat their first pair in the sixth place.  Per neighbour slot the
+// edge midpoint gets its coordinates for s and for the neighbour.  Per
+// (r, theta) and slot, the edge flux enters the update of s with one signed
+// coefficient (the donor-cell coefficients of the slot) applied to the state
+// of the edge's upwind side, and a flag tells whether that side is s.
+rt_status build_mapr(rt_ctx* c, const KsTables& T) {
+  const GeodesicGrid& G = c->grid;
+  const int ns = c->ns, ne = (int)G.edge.size();
+  const size_t nrt = (size_t)c->n[0] * c->n[1];
+  std::vector<double> E((size_t)ns * 6);
+  for (int s = 0; s < ns; ++s) {
+    const double* n = G.dir[s].data();
+    // e1 = normalise(a x n) for the coordinate axis a least aligned with n
+    int k = 0;
+    for (int q = 1; q < 3; ++q)
+      if (std::fabs(n[q]) < std::fabs(n[k])) k = q;
+    double a[3] = {0, 0, 0};
+    a[k] = 1.0;
+    double e1[3] = {a[1] * n[2] - a[2] * n[1], a[2] * n[0] - a[0] * n[2], a[0] * n[1] - a[1] * n[0]};
+    const double l = std::sqrt(e1[0] * e1[0] + e1[1] * e1[1] + e1[2] * e1[2]);
+    for (int q = 0; q < 3; ++q) e1[q] /= l;
+    const double e2[3] = {n[1] * e1[2] - n[2] * e1[1], n[2] * e1[0] - n[0] * e1[2], n[0] * e1[1] - n[1] * e1[0]};
+    for (int q = 0; q < 3; ++q) {
+      E[(size_t)s * 6 + q] = e1[q];
+      E[(size_t)s * 6 + 3 + q] = e2[q];
+    }
+  }
+  auto coords = [&](int s, const double* x, double out[2]) {
+    const double* n = G.dir[s].data();
+    const double d = x[0] * n[0] + x[1] * n[1] + x[2] * n[2];
+    double p[3];
+    for (int q = 0; q < 3; ++q) p[q] = x[q] / d - n[q];
+    const double* e = &E[(size_t)s * 6];
+    out[0] = p[0] * e[0] + p[1] * e[1] + p[2] * e[2];
+    out[1] = p[0] * e[3] + p[1] * e[4] + p[2] * e[5];
+  };
+  std::vector<int> pair((size_t)ns * KS_DEG * 2);
+  std::vector<double> minv((size_t)ns * KS_DEG * 4), pq((size_t)ns * KS_ROW * 4, 0.0);
+  for (int s = 0; s < ns; ++s) {
+    const int k0 = T.inc_off[s], deg = T.inc_off[s + 1] - k0;
+    if (deg < 3) return fail(RT_E_ARG, "rt_set_metric: a direction has fewer than 3 neighbours");
+    double xy[KS_DEG][2];
+    std::vector<std::pair<double, int>> ang;
+    for (int j = 0; j < deg; ++j) {
+      coords(s, G.dir[T.inc_other[k0 + j]].data(), xy[j]);
+      ang.push_back({std::atan2(xy[j][1], xy[j][0]), j});
+    }
+    std::sort(ang.begin(), ang.end());
+    // the cycle starts at the neighbour with the smallest direction index (the
+    // kernel breaks ties between planes of equal slope by this order)
+    std::rotate(ang.begin(), std::min_element(ang.begin(), ang.end(),
+                                              [&](const std::pair<double, int>& x, const std::pair<double, int>& y) {
+                                                return T.inc_other[k0 + x.second] < T.inc_other[k0 + y.second];
+                                              }),
+                ang.end());
+    for (int i = 0; i < KS_DEG; ++i) {
+      const int ja = ang[i % deg].second, jb = ang[(i + 1) % deg].second;
+      const double* pa = xy[ja];
+      const double* pb = xy[jb];
+      const double det = pa[0] * pb[1] - pa[1] * pb[0];
+      pair[((size_t)s * KS_DEG + i) * 2 + 0] = T.inc_other[k0 + ja];
+      pair[((size_t)s * KS_DEG + i) * 2 + 1] = T.inc_other[k0 + jb];
+      double* m = &minv[((size_t)s * KS_DEG + i) * 4];
+      m[0] = pb[1] / det;
+      m[1] = -pa[1] / det;
+      m[2] = -pb[0] / det;
+      m[3] = pa[0] / det;
+    }
+    for (int j = 0; j < deg; ++j) {
+      const int k = k0 + j, e = T.inc_edge[k];
+      double* w = &pq[((size_t)s * KS_ROW + 1 + j) * 4];
+      coords(s, G.emid[e].data(), w);
+      coords(T.inc_other[k], G.emid[e].data(), w + 2);
+    }
+  }
+  std::vector<double> coef;
+  std::vector<unsigned char> self;
+  try {
+    coef.assign(nrt * ns * KS_ROW, 0.0);
+    self.assign(nrt * ns, 0);
+  } catch (const std::bad_alloc&) {
+    return fail(RT_E_NOMEM, "rt_set_metric: host allocation failed");
+  }
+  for (size_t q = 0; q < nrt; ++q)
+    for (int s = 0; s < ns; ++s) {
+      const double scale = T.fp[((size_t)s * nrt + q) * 4 + 3] * T.dV[q] / G.w[s];
+      const int k0 = T.inc_off[s], deg = T.inc_off[s + 1] - k0;
+      unsigned char f = 0;
+      for (int j = 0; j < deg; ++j) {
+        const int k = k0 + j;
+        const double vP = T.ve[(q * ne + T.inc_edge[k]) * 2], vN = T.ve[(q * ne + T.inc_edge[k]) * 2 + 1];
+        // one of vP (upwind: the edge's first direction), vN (its second) is zero
+        const bool first = T.inc_side[k] > 0;
+        if (first ? vP != 0.0 : vN != 0.0) f |= (unsigned char)(1u << (1 + j));
+        coef[(q * ns + s) * KS_ROW + 1 + j] = (first ? scale : -scale) * (vP + vN);
+      }
+      self[q * ns + s] = f;
+    }
+  rt_status st = RT_OK;
+  if ((st = upload(&c->d_mp_pair, pair)) || (st = upload_as(c, &c->d_mp_minv, minv)) ||
+      (st = upload_as(c, &c->d_mp_pq, pq)) || (st = upload_as(c, &c->d_mp_coef, coef)) ||
+      (st = upload(&c->d_mp_self, self)) ||
+      (st = alloc((char**)&c->d_mp_grad, (size_t)2 * c->ns * c->nc * c->elem)))
+    return st;
+  c->mapr = true;
+  return RT_OK;
+}
+
 rt_status set_kerr_schild(rt_ctx* c, double M, double a, double cfl) {
   KsTables T;
   try {
@@ -233,6 +348,7 @@ rt_status set_kerr_schild(rt_ctx* c, double M, double a, double cfl) {
       (st = upload(&c->d_einv, T.einv)) || (st = upload(&c->d_inc, inc)) ||
       (st = alloc((char**)&c->d_angD, (size_t)c->ns * c->nc * c->elem)))
     return st;
+  if (c->desc.angular_recon == RT_AREC_MAPR && (st = build_mapr(c, T))) return st;
   c->dt_max = T.dt_max;
   c->curved = true;
   return RT_OK;
@@ -271,6 +387,8 @@ rt_status rt_init_grid(const rt_grid_desc* d, rt_ctx** out) {
   if (d->precision != RT_FP64 && d->precision != RT_FP32_TRANSPORT)
     return fail(RT_E_ARG, "rt_init_grid: bad precision");
   if (d->limiter != RT_LIM_MC && d->limiter != RT_LIM_MINMOD) return fail(RT_E_ARG, "rt_init_grid: bad limiter");
+  if (d->angular_recon != RT_AREC_DONOR && d->angular_recon != RT_AREC_MAPR)
+    return fail(RT_E_ARG, "rt_init_grid: bad angular_recon");
   if (!(d->abar >= 0.0) || !(d->rho_floor >= 0.0)) return fail(RT_E_ARG, "rt_init_grid: abar, rho_floor >= 0");
   long long nc = (long long)d->n[0] * d->n[1] * d->n[2];
   // the stage kernels address one direction's plane with 32-bit byte offsets
@@ -694,6 +812,12 @@ void rt_destroy(rt_ctx* c) {
   release(c->d_pnout);
   release(c->d_plnb);
   release(c->d_angD);
+  release(c->d_mp_pair);
+  release(c->d_mp_minv);
+  release(c->d_mp_pq);
+  release(c->d_mp_coef);
+  release(c->d_mp_self);
+  release(c->d_mp_grad);
   for (auto& t : c->timed) {
     (void)hipEventDestroy(t.a);
     (void)hipEventDestroy(t.b);

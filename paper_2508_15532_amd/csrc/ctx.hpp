@@ -44,6 +44,15 @@ struct rt_ctx {
   int* d_pnout = nullptr;        // [npatch] directions owned by the patch (the list's head)
   int* d_plnb = nullptr;         // [ns][KS_ROW] positions of a direction's row set in its patch's list
   void* d_angD = nullptr;        // [ns][nc] angular divergence scratch
+  // MAPR edge states (angular_recon = RT_AREC_MAPR), transport type unless noted
+  bool mapr = false;
+  int* d_mp_pair = nullptr;      // [ns][KS_DEG][2] consecutive neighbour pairs (directions)
+  void* d_mp_minv = nullptr;     // [ns][KS_DEG][4] inverse of the pair's gnomonic coordinates
+  void* d_mp_pq = nullptr;       // [ns][KS_ROW][4] per neighbour slot: the edge midpoint in the
+                                 // direction's and in the neighbour's gnomonic coordinates
+  void* d_mp_coef = nullptr;     // [N1 N2][ns][KS_ROW] edge flux coefficient per slot
+  unsigned char* d_mp_self = nullptr;  // [N1 N2][ns] bit j: slot j's upwind side is the direction
+  void* d_mp_grad = nullptr;     // [ns][2][nc] slope per direction and cell
 
   // device grid tables
   double* d_dir = nullptr;    // [3][ns] n-hat components, component-major

@@ -17,7 +17,7 @@ def gpu_context(wl, precision="fp64", limiter="mc", cfl=0.4):
         ctx = P.RTContext(wl["n"], wl["xlo"], wl["xhi"], wl["generation"], weights=wl["weights"],
                           precision=precision, bc=wl["bc"], bc_hi=wl.get("bc_hi"), limiter=limiter,
                           coords="logr_theta_phi", pole_zero_rows=wl["pole_rows"],
-                          n0_cut=wl["n0_cut"])
+                          n0_cut=wl["n0_cut"], angular_recon=wl.get("angular_recon", "donor"))
         ctx.set_metric("kerr_schild", M=wl["M"], a=wl["a"], cfl=wl.get("cfl", cfl))
     else:
         ctx = P.RTContext(wl["n"], wl["xlo"], wl["xhi"], wl["generation"], weights=wl["weights"],

@@ -69,6 +69,7 @@ def _desc(N, **kw):
     (dict(generation=6), b"generation"),
     (dict(precision=7), b"precision"),
     (dict(limiter=3), b"limiter"),
+    (dict(angular_recon=2), b"angular_recon"),
     (dict(bc_lo=(0, 0, 0), bc_hi=(1, 0, 0)), b"periodic"),
     (dict(coords=5), b"coords"),
     (dict(weights=4), b"weights"),

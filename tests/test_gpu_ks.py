@@ -263,3 +263,64 @@ def test_ks_generation3(precision):
         _check_fp64(g, o, wl)
     else:
         _check_fp32(g, o)
+
+
+def _mapr(wl):
+    wl = dict(wl)
+    wl["angular_recon"] = "mapr"
+    return wl
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_ks_mapr_torus_reduced(precision):
+    """MAPR angular edge states on the reduced torus (12x16x8, generation 1,
+    3 steps); the result also differs from the donor-cell one, so the MAPR
+    kernels are the ones that ran."""
+    wl, I0 = _case()
+    wm = _mapr(wl)
+    _say(f"torus_ks mapr {precision} 12x16x8 g1 3 steps")
+    g = gpu_run(wm, 3, precision=precision, I0=I0)
+    o = oracle_run(wm, 3, I0=I0)
+    if precision == "fp64":
+        _check_fp64(g, o, wm)
+        d = gpu_run(wl, 3, precision=precision, I0=I0)
+        assert rel_max(g["I"], d["I"]) > 1e-6
+    else:
+        _check_fp32(g, o)
+
+
+def test_ks_mapr_inside_horizon_generation2():
+    """MAPR with n_0 changing sign and falling below the cut (r_in inside the
+    horizon), generation 2, minmod, scattering, 2 steps, FP64."""
+    wl, I0 = _case(n=(10, 12, 6), generation=2, pole_rows=0, scattering=True, r_in=1.2, r_out=8.0)
+    wm = _mapr(wl)
+    _say("torus_ks mapr fp64 inside horizon 10x12x6 g2 2 steps minmod")
+    g = gpu_run(wm, 2, I0=I0, limiter="minmod")
+    o = oracle_run(wm, 2, I0=I0, limiter=1)
+    _check_fp64(g, o, wm)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_ks_mapr_generation3_ragged(precision):
+    """MAPR with 642 directions on 5x8x20 cells (800: the last workgroup of each
+    direction is partly filled), 2 steps."""
+    wl, I0 = _case(n=(5, 8, 20), generation=3, pole_rows=1)
+    wm = _mapr(wl)
+    _say(f"torus_ks mapr {precision} g3 5x8x20 2 steps")
+    g = gpu_run(wm, 2, precision=precision, I0=I0)
+    o = oracle_run(wm, 2, I0=I0)
+    if precision == "fp64":
+        _check_fp64(g, o, wm)
+    else:
+        _check_fp32(g, o)
+
+
+def test_ks_mapr_flat_spherical():
+    """M = 0 (flat space in ln r, theta, phi) with MAPR states, generation 2,
+    zero-incoming outside, 3 steps, FP64."""
+    wl, I0 = _case(n=(8, 10, 6), generation=2, pole_rows=1, M=0.0, a=0.0, r_in=2.0, r_out=9.0)
+    wm = _mapr(wl)
+    _say("flat spherical mapr fp64 8x10x6 g2 3 steps")
+    g = gpu_run(wm, 3, I0=I0)
+    o = oracle_run(wm, 3, I0=I0)
+    _check_fp64(g, o, wm)
