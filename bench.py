@@ -71,7 +71,8 @@ def make_context(wl, precision, P):
     if wl.get("metric") == "kerr_schild":
         ctx = P.RTContext(wl["n"], wl["xlo"], wl["xhi"], wl["generation"], weights=wl["weights"],
                           precision=precision, bc=wl["bc"], bc_hi=wl["bc_hi"],
-                          coords="logr_theta_phi", pole_zero_rows=wl["pole_rows"], n0_cut=wl["n0_cut"])
+                          coords="logr_theta_phi", pole_zero_rows=wl["pole_rows"], n0_cut=wl["n0_cut"],
+                          angular_recon=wl.get("angular_recon", "donor"))
         dt = ctx.set_metric("kerr_schild", M=wl["M"], a=wl["a"], cfl=wl["cfl"])
         return ctx, dt
     ctx = P.RTContext(wl["n"], wl["xlo"], wl["xhi"], wl["generation"], weights=wl["weights"],
@@ -195,6 +196,8 @@ def main():
                     help="skip the extra line with K steps advanced by one rt_step call")
     ap.add_argument("--no-torus", action="store_true",
                     help="skip the Kerr-Schild torus line (256x128x64 x 162, FP32)")
+    ap.add_argument("--no-mapr", action="store_true",
+                    help="skip the torus line with MAPR angular states (256x128x64 x 162, FP32)")
     ap.add_argument("--no-big-torus", action="store_true",
                     help="skip the large turbulent-torus line (384x192x128 x 642, FP32, 3 steps)")
     ap.add_argument("--moments-only", action="store_true",
@@ -301,6 +304,31 @@ def main():
             "ms_per_step": 1e3 * tr["wall"] / args.steps,
             "kernels_ms_per_step": {k: v[1] / args.steps for k, v in tr["ktimes"].items() if v[0]},
             "finite": tr["finite"]}
+    if not args.no_mapr:
+        # the same torus with MAPR angular edge states (two kernels in place of the
+        # donor-cell angular kernel); algorithmic HBM bytes of the pair per
+        # cell-direction: slope pass reads I, writes the 2-component slope; flux
+        # pass reads I and both slope components, writes D (neighbour rows are
+        # cache reuse, the per-(r, theta) coefficient rows are shared along phi)
+        msteps = min(args.steps, 5)
+        print(f"bench: torus_ks mapr fp32 256x128x64 x 162, {msteps} steps", file=sys.stderr, flush=True)
+        mw = dict(W.torus_ks(), angular_recon="mapr")
+        mr = run_form(mw, "fp32", msteps, 1, torch, P, per_call=True)
+        kms = {k: v[1] / msteps for k, v in mr["ktimes"].items() if v[0]}
+        entry = {
+            "workload": "Kerr-Schild a=0.9 torus, 256x128x64 x 162 directions, MAPR angular states, "
+                        "FP32 transport",
+            "value": mr["ns"] * mr["nc"] * msteps / mr["wall"],
+            "unit": "cell-direction updates/s",
+            "ms_per_step": 1e3 * mr["wall"] / msteps,
+            "kernels_ms_per_step": kms,
+            "finite": mr["finite"]}
+        n_ang, ms_ang = mr["ktimes"].get("angular", (0, 0.0))
+        if n_ang:
+            per_launch_ms = ms_ang / n_ang          # one evaluation per stage
+            entry["angular_mapr_ms_per_launch"] = per_launch_ms
+            entry["angular_mapr_hbm_GBps"] = 7 * mr["elem"] * mr["ns"] * mr["nc"] / (per_launch_ms * 1e-3) / 1e9
+        out["torus_ks_mapr"] = entry
     if not args.no_big_torus:
         # the largest configuration: 6.1e9 cell-directions, 24 GB per FP32 intensity copy
         print("bench: turbulent torus fp32 384x192x128 x 642, 1 warmup + 3 timed steps",

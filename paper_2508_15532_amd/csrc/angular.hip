@@ -201,17 +201,29 @@ hipError_t launch_cw(rt_ctx* c, const void* I, hipStream_t st) {
 // zeroed intensities), so rounding must not choose among them: every plane with
 // |g|^2 within the relative band tie_band<S>() of the smallest counts as
 // minimal and the first of them in the cyclic order is taken.  One thread per
-// cell, one direction per blockIdx.y, so the pair tables are uniform (scalar)
-// loads.
+// cell and one direction per workgroup (uniform, scalar table loads); see
+// mapr_block for the order of the workgroups.
 template <typename S>
 __device__ constexpr S tie_band() { return sizeof(S) == 8 ? S(1e-8) : S(1e-4); }
 
+// Workgroup -> (256-cell chunk, direction).  Consecutive workgroups go to the
+// eight XCDs in turn, so workgroup b runs on XCD b % 8; each XCD takes whole
+// chunks (chunk = 8 k + xcd) and runs all directions of a chunk back to back,
+// so the neighbour rows of the chunk (ns x 256 cells) are reused from that
+// XCD's L2.  The grid has ceil(chunks / 8) * 8 * ns workgroups; those past the
+// last chunk exit.
+__device__ inline long long mapr_block(int ns, int& s) {
+  const unsigned b = blockIdx.x, local = b >> 3;
+  s = (int)(local % (unsigned)ns);
+  return (long long)(local / (unsigned)ns) * 8 + (b & 7u);
+}
+
 template <typename S>
 __global__ void __launch_bounds__(256)
-k_mapr_slope(long long nc, const S* __restrict__ I, S* __restrict__ G, const int* __restrict__ pair,
-             const S* __restrict__ minv) {
-  const long long c = (long long)blockIdx.x * 256 + threadIdx.x;
-  const int s = blockIdx.y;
+k_mapr_slope(long long nc, int ns, const S* __restrict__ I, S* __restrict__ G,
+             const int* __restrict__ pair, const S* __restrict__ minv) {
+  int s;
+  const long long c = mapr_block(ns, s) * 256 + threadIdx.x;
   if (c >= nc) return;
   const S Is = I[(long long)s * nc + c];
   const int* pr = pair + s * KS_DEG * 2;
@@ -244,11 +256,11 @@ k_mapr_slope(long long nc, const S* __restrict__ I, S* __restrict__ G, const int
 // I_u where that is negative (u = s or its neighbour, by the slot's flag).
 template <typename S>
 __global__ void __launch_bounds__(256)
-k_mapr_flux(long long nc, int n3, const S* __restrict__ I, const S* __restrict__ G, S* __restrict__ D,
-            const int* __restrict__ nbr, const S* __restrict__ pq, const S* __restrict__ coef,
-            const unsigned char* __restrict__ self) {
-  const long long c = (long long)blockIdx.x * 256 + threadIdx.x;
-  const int s = blockIdx.y, ns = gridDim.y;
+k_mapr_flux(long long nc, int n3, int ns, const S* __restrict__ I, const S* __restrict__ G,
+            S* __restrict__ D, const int* __restrict__ nbr, const S* __restrict__ pq,
+            const S* __restrict__ coef, const unsigned char* __restrict__ self) {
+  int s;
+  const long long c = mapr_block(ns, s) * 256 + threadIdx.x;
   if (c >= nc) return;
   const long long q = c / n3;  // (i1, i2) position
   const S* a = coef + (q * ns + s) * KS_ROW;
@@ -277,14 +289,17 @@ k_mapr_flux(long long nc, int n3, const S* __restrict__ I, const S* __restrict__
 
 template <typename S>
 hipError_t launch_mapr(rt_ctx* c, const void* I, hipStream_t st) {
-  const dim3 grid((unsigned)((c->nc + 255) / 256), (unsigned)c->ns), block(256);
+  const long long chunks8 = ((c->nc + 255) / 256 + 7) / 8 * 8;
+  const long long nblk = chunks8 * c->ns;
+  if (nblk > 0xffffffffLL) return hipErrorInvalidConfiguration;
+  const dim3 grid((unsigned)nblk), block(256);
   const S* in = (const S*)I;
   S* G = (S*)c->d_mp_grad;
-  hipLaunchKernelGGL((k_mapr_slope<S>), grid, block, 0, st, c->nc, in, G, c->d_mp_pair,
+  hipLaunchKernelGGL((k_mapr_slope<S>), grid, block, 0, st, c->nc, c->ns, in, G, c->d_mp_pair,
                      (const S*)c->d_mp_minv);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_mapr_flux<S>), grid, block, 0, st, c->nc, c->n[2], in, (const S*)G,
+  hipLaunchKernelGGL((k_mapr_flux<S>), grid, block, 0, st, c->nc, c->n[2], c->ns, in, (const S*)G,
                      (S*)c->d_angD, c->d_inc, (const S*)c->d_mp_pq, (const S*)c->d_mp_coef,
                      c->d_mp_self);
   return hipGetLastError();

@@ -127,19 +127,22 @@ def test_ks_coordinate_moments():
     assert (Rc - ref).abs().max() <= 1e-12 * ref.abs().max()
 
 
-def test_ks_full_size_fp32_sampled():
+@pytest.mark.parametrize("recon", ["donor", "mapr"])
+def test_ks_full_size_fp32_sampled(recon):
     """The a = 0.9 torus at 256x128x64, generation 2 (162 directions), FP32,
-    one step in one launch sequence; sub-boxes away from the r and theta
-    boundaries are recomputed by the oracle with a 4-cell halo (the reach of
-    one predictor-corrector step) and compared on their interiors."""
+    one step in one launch sequence, donor-cell or MAPR angular states;
+    sub-boxes away from the r and theta boundaries are recomputed by the
+    oracle with a 4-cell halo (the reach of one predictor-corrector step) and
+    compared on their interiors."""
     n = (256, 128, 64)
     wl = W.torus_ks(n=n, generation=2)
+    wl["angular_recon"] = recon
     ns = 162
     rng = np.random.default_rng(21)
     I0 = rng.uniform(0.5, 1.5, size=(ns,) + n).astype(np.float32)
     ctx = gpu_context(wl, precision="fp32")
     dt = ctx.dt_max
-    _say(f"torus_ks fp32 256x128x64 g2 1 step dt={dt}")
+    _say(f"torus_ks {recon} fp32 256x128x64 g2 1 step dt={dt}")
     I = torch.as_tensor(I0).reshape(ns, -1).cuda().contiguous()
     T = torch.as_tensor(wl["T"], dtype=F64).reshape(-1).cuda().contiguous()
     ctx.step(I, T, dt, 1)
