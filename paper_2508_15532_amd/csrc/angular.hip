@@ -221,29 +221,33 @@ __device__ inline long long mapr_block(int ns, int& s) {
 template <typename S>
 __global__ void __launch_bounds__(256)
 k_mapr_slope(long long nc, int ns, const S* __restrict__ I, S* __restrict__ G,
-             const int* __restrict__ pair, const S* __restrict__ minv) {
+             const int* __restrict__ ring, const S* __restrict__ minv) {
   int s;
   const long long c = mapr_block(ns, s) * 256 + threadIdx.x;
   if (c >= nc) return;
   const S Is = I[(long long)s * nc + c];
-  const int* pr = pair + s * KS_DEG * 2;
+  const int* r = ring + s * KS_ROW;  // [0] neighbour count, [1..6] cyclic order
+  const bool pentagon = r[0] == 5;   // uniform: its sixth pair is degenerate
   const S* m = minv + s * KS_DEG * 4;
+  S d[KS_DEG];
+#pragma unroll
+  for (int j = 0; j < KS_DEG; ++j) d[j] = I[(long long)r[1 + j] * nc + c] - Is;
   S h0[KS_DEG], h1[KS_DEG], nn[KS_DEG];
   S lo = 0;
 #pragma unroll
   for (int i = 0; i < KS_DEG; ++i) {
-    const S dA = I[(long long)pr[2 * i] * nc + c] - Is;
-    const S dB = I[(long long)pr[2 * i + 1] * nc + c] - Is;
+    const S dA = d[i], dB = d[(i + 1) % KS_DEG];
     h0[i] = m[4 * i] * dA + m[4 * i + 1] * dB;
     h1[i] = m[4 * i + 2] * dA + m[4 * i + 3] * dB;
     nn[i] = h0[i] * h0[i] + h1[i] * h1[i];
+    if (i == KS_DEG - 1 && pentagon) continue;
     lo = i == 0 ? nn[i] : (nn[i] < lo ? nn[i] : lo);
   }
   const S thr = lo * (S(1) + tie_band<S>());
   S g0 = h0[0], g1 = h1[0];
 #pragma unroll
   for (int i = KS_DEG - 1; i >= 0; --i)
-    if (nn[i] <= thr) {
+    if (nn[i] <= thr && !(i == KS_DEG - 1 && pentagon)) {
       g0 = h0[i];
       g1 = h1[i];
     }
@@ -295,7 +299,7 @@ hipError_t launch_mapr(rt_ctx* c, const void* I, hipStream_t st) {
   const dim3 grid((unsigned)nblk), block(256);
   const S* in = (const S*)I;
   S* G = (S*)c->d_mp_grad;
-  hipLaunchKernelGGL((k_mapr_slope<S>), grid, block, 0, st, c->nc, c->ns, in, G, c->d_mp_pair,
+  hipLaunchKernelGGL((k_mapr_slope<S>), grid, block, 0, st, c->nc, c->ns, in, G, c->d_mp_ring,
                      (const S*)c->d_mp_minv);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;

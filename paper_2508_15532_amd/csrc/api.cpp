@@ -126,7 +126,7 @@ rt_status upload(T** dst, const std::vector<T>& v) {
 // neighbour with the smallest index), give the consecutive pairs (a, b); the slope of
 // the plane through (0, I_s), (p_a, I_a), (p_b, I_b) is
 // g = [p_a; p_b]^-1 (I_a - I_s, I_b - I_s), and the kernels keep the inverse.
-// Pentagons repeat their first pair in the sixth place.  Per neighbour slot the
+// Pentagons have five pairs (the sixth is skipped).  Per neighbour slot the
 // edge midpoint gets its coordinates for s and for the neighbour.  Per
 // (r, theta) and slot, the edge flux enters the update of s with one signed
 // coefficient (the donor-cell coefficients of the slot) applied to the state
@@ -162,11 +162,11 @@ rt_status build_mapr(rt_ctx* c, const KsTables& T) {
     out[0] = p[0] * e[0] + p[1] * e[1] + p[2] * e[2];
     out[1] = p[0] * e[3] + p[1] * e[4] + p[2] * e[5];
   };
-  std::vector<int> pair((size_t)ns * KS_DEG * 2);
+  std::vector<int> ring((size_t)ns * KS_ROW);
   std::vector<double> minv((size_t)ns * KS_DEG * 4), pq((size_t)ns * KS_ROW * 4, 0.0);
   for (int s = 0; s < ns; ++s) {
     const int k0 = T.inc_off[s], deg = T.inc_off[s + 1] - k0;
-    if (deg < 3) return fail(RT_E_ARG, "rt_set_metric: a direction has fewer than 3 neighbours");
+    if (deg < 5) return fail(RT_E_ARG, "rt_set_metric: MAPR needs 5 or 6 neighbours per direction");
     double xy[KS_DEG][2];
     std::vector<std::pair<double, int>> ang;
     for (int j = 0; j < deg; ++j) {
@@ -181,13 +181,18 @@ rt_status build_mapr(rt_ctx* c, const KsTables& T) {
                                                 return T.inc_other[k0 + x.second] < T.inc_other[k0 + y.second];
                                               }),
                 ang.end());
+    // ring slots: [0] the number of neighbours, [1..6] the neighbours in cyclic
+    // order, [7] unused; pair i is slots 1 + i and 1 + (i + 1) mod 6 (a pentagon
+    // repeats its first neighbour in slot 6, so its pair 4 closes the cycle;
+    // its pair 5 is degenerate and the kernel skips it)
+    ring[(size_t)s * KS_ROW] = deg;
+    ring[(size_t)s * KS_ROW + KS_ROW - 1] = s;
     for (int i = 0; i < KS_DEG; ++i) {
       const int ja = ang[i % deg].second, jb = ang[(i + 1) % deg].second;
       const double* pa = xy[ja];
       const double* pb = xy[jb];
       const double det = pa[0] * pb[1] - pa[1] * pb[0];
-      pair[((size_t)s * KS_DEG + i) * 2 + 0] = T.inc_other[k0 + ja];
-      pair[((size_t)s * KS_DEG + i) * 2 + 1] = T.inc_other[k0 + jb];
+      ring[(size_t)s * KS_ROW + 1 + i] = T.inc_other[k0 + ja];
       double* m = &minv[((size_t)s * KS_DEG + i) * 4];
       m[0] = pb[1] / det;
       m[1] = -pa[1] / det;
@@ -225,7 +230,7 @@ rt_status build_mapr(rt_ctx* c, const KsTables& T) {
       self[q * ns + s] = f;
     }
   rt_status st = RT_OK;
-  if ((st = upload(&c->d_mp_pair, pair)) || (st = upload_as(c, &c->d_mp_minv, minv)) ||
+  if ((st = upload(&c->d_mp_ring, ring)) || (st = upload_as(c, &c->d_mp_minv, minv)) ||
       (st = upload_as(c, &c->d_mp_pq, pq)) || (st = upload_as(c, &c->d_mp_coef, coef)) ||
       (st = upload(&c->d_mp_self, self)) ||
       (st = alloc((char**)&c->d_mp_grad, (size_t)2 * c->ns * c->nc * c->elem)))
@@ -812,7 +817,7 @@ void rt_destroy(rt_ctx* c) {
   release(c->d_pnout);
   release(c->d_plnb);
   release(c->d_angD);
-  release(c->d_mp_pair);
+  release(c->d_mp_ring);
   release(c->d_mp_minv);
   release(c->d_mp_pq);
   release(c->d_mp_coef);

@@ -46,7 +46,7 @@ struct rt_ctx {
   void* d_angD = nullptr;        // [ns][nc] angular divergence scratch
   // MAPR edge states (angular_recon = RT_AREC_MAPR), transport type unless noted
   bool mapr = false;
-  int* d_mp_pair = nullptr;      // [ns][KS_DEG][2] consecutive neighbour pairs (directions)
+  int* d_mp_ring = nullptr;      // [ns][KS_ROW] neighbour count, neighbours in cyclic order
   void* d_mp_minv = nullptr;     // [ns][KS_DEG][4] inverse of the pair's gnomonic coordinates
   void* d_mp_pq = nullptr;       // [ns][KS_ROW][4] per neighbour slot: the edge midpoint in the
                                  // direction's and in the neighbour's gnomonic coordinates
