@@ -258,7 +258,9 @@ k_mapr_slope(long long nc, int ns, const S* __restrict__ I, S* __restrict__ G,
 // Pass 2: D'_s = sum_j a_sj R_j over the neighbour slots j of s, with R_j the
 // state at the edge midpoint of the slot's upwind side: I_u + g_u . p_u(m),
 // I_u where that is negative (u = s or its neighbour, by the slot's flag).
-template <typename S>
+// WROW: n3 is a multiple of 64, so a wave's 64 cells share one (i1, i2)
+// position and its coefficient row and flags are loaded once per wave.
+template <typename S, bool WROW>
 __global__ void __launch_bounds__(256)
 k_mapr_flux(long long nc, int n3, int ns, const S* __restrict__ I, const S* __restrict__ G,
             S* __restrict__ D, const int* __restrict__ nbr, const S* __restrict__ pq,
@@ -266,7 +268,8 @@ k_mapr_flux(long long nc, int n3, int ns, const S* __restrict__ I, const S* __re
   int s;
   const long long c = mapr_block(ns, s) * 256 + threadIdx.x;
   if (c >= nc) return;
-  const long long q = c / n3;  // (i1, i2) position
+  long long q = c / n3;  // (i1, i2) position
+  if (WROW) q = __builtin_amdgcn_readfirstlane((int)q);
   const S* a = coef + (q * ns + s) * KS_ROW;
   const unsigned f = self[q * ns + s];
   const int* o = nbr + s * KS_ROW;
@@ -303,9 +306,14 @@ hipError_t launch_mapr(rt_ctx* c, const void* I, hipStream_t st) {
                      (const S*)c->d_mp_minv);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_mapr_flux<S>), grid, block, 0, st, c->nc, c->n[2], c->ns, in, (const S*)G,
-                     (S*)c->d_angD, c->d_inc, (const S*)c->d_mp_pq, (const S*)c->d_mp_coef,
-                     c->d_mp_self);
+  if (c->n[2] % 64 == 0)
+    hipLaunchKernelGGL((k_mapr_flux<S, true>), grid, block, 0, st, c->nc, c->n[2], c->ns, in,
+                       (const S*)G, (S*)c->d_angD, c->d_inc, (const S*)c->d_mp_pq,
+                       (const S*)c->d_mp_coef, c->d_mp_self);
+  else
+    hipLaunchKernelGGL((k_mapr_flux<S, false>), grid, block, 0, st, c->nc, c->n[2], c->ns, in,
+                       (const S*)G, (S*)c->d_angD, c->d_inc, (const S*)c->d_mp_pq,
+                       (const S*)c->d_mp_coef, c->d_mp_self);
   return hipGetLastError();
 }
 
