@@ -327,3 +327,28 @@ def test_ks_mapr_flat_spherical():
     g = gpu_run(wm, 3, I0=I0)
     o = oracle_run(wm, 3, I0=I0)
     _check_fp64(g, o, wm)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_ks_mapr_generation0_pentagons(precision):
+    """MAPR on the icosahedron (12 directions, all pentagons: five planes each,
+    the padded sixth skipped), 6x8x10 cells, 3 steps."""
+    wl, I0 = _case(n=(6, 8, 10), generation=0, pole_rows=1)
+    wm = _mapr(wl)
+    _say(f"torus_ks mapr {precision} g0 6x8x10 3 steps")
+    g = gpu_run(wm, 3, precision=precision, I0=I0)
+    o = oracle_run(wm, 3, I0=I0)
+    if precision == "fp64":
+        _check_fp64(g, o, wm)
+    else:
+        _check_fp32(g, o)
+
+
+def test_ks_mapr_generation4():
+    """MAPR with 2562 directions (two-pass kernels), 4x6x70 cells, 1 step, FP64."""
+    wl, I0 = _case(n=(4, 6, 70), generation=4, pole_rows=1)
+    wm = _mapr(wl)
+    _say("torus_ks mapr fp64 g4 4x6x70 1 step")
+    g = gpu_run(wm, 1, I0=I0)
+    o = oracle_run(wm, 1, I0=I0)
+    _check_fp64(g, o, wm)
