@@ -137,10 +137,11 @@ class KerrSchildLogR:
 
     kind = "kerr_schild"
 
-    def __init__(self, n, xlo, xhi, grid, a, M=1.0, fd_h=1e-3, recon="donor"):
+    def __init__(self, n, xlo, xhi, grid, a, M=1.0, fd_h=1e-3, recon="donor", mapr_tie_rtol=None):
         if recon not in ("donor", "mapr"):
             raise ValueError(recon)
         self.recon = recon
+        self.mapr_tie_rtol = mapr_tie_rtol      # None: the FP64 band of oracle.mapr
         self.n = tuple(int(v) for v in n)
         self.xlo, self.xhi = tuple(map(float, xlo)), tuple(map(float, xhi))
         self.dx = tuple((b - c) / m for c, b, m in zip(self.xlo, self.xhi, self.n))
@@ -261,7 +262,8 @@ class KerrSchildLogR:
             from . import mapr
             if not hasattr(self, "_ring"):
                 self._ring = mapr.rings(g)
-            first, second = mapr.edge_states(g, I, self._ring)
+            tie = mapr.TIE_RTOL if self.mapr_tie_rtol is None else self.mapr_tie_rtol
+            first, second = mapr.edge_states(g, I, self._ring, tie)
             Iup = torch.where(v > 0, first, second)
         else:
             Iup = torch.where(v > 0, I[es], I[et])

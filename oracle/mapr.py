@@ -1,4 +1,4 @@
-"""MAPR angular reconstruction on the geodesic grid (Sec. 3.5: the states at
+"""MAPR angular reconstruction on the geodesic grid (Sec. 3.4; the states at
 the Voronoi edges for the angular fluxes; the paper names the minimum-angle
 plane reconstruction of its cited source and donor cell as the alternative).
 
@@ -31,7 +31,11 @@ import numpy as np
 import torch
 
 F64 = torch.float64
-TIE_RTOL = 1e-8     # relative |g|^2 band of the minimal planes (FP64)
+# relative |g|^2 band of the minimal planes: at the rounding level of the
+# arithmetic that compares them, 1e-8 for the FP64 form and 1e-4 for the FP32
+# transport form (whose slopes carry ~1e-7 relative rounding)
+TIE_RTOL = 1e-8
+TIE_RTOL_FP32 = 1e-4
 
 
 def gnomonic(n_s, x):
@@ -71,7 +75,7 @@ def pair_slope(pa, pb, dA, dB):
             + beta[..., None] * torch.as_tensor(pb, dtype=F64))
 
 
-def slopes(grid, I, ring=None):
+def slopes(grid, I, ring=None, tie_rtol=TIE_RTOL):
     """Minimum-norm slope vector g_s for every direction and cell: [Ns, *cells, 3]."""
     ring = ring if ring is not None else rings(grid)
     I = torch.as_tensor(I, dtype=F64)
@@ -86,7 +90,7 @@ def slopes(grid, I, ring=None):
             cand.append(pair_slope(P[a], P[b], I[r[a]] - I[s], I[r[b]] - I[s]))
         cand = torch.stack(cand)                               # [deg, *cells, 3]
         norms = (cand * cand).sum(-1)                          # [deg, *cells]
-        minimal = norms <= norms.min(0).values * (1.0 + TIE_RTOL)
+        minimal = norms <= norms.min(0).values * (1.0 + tie_rtol)
         first = minimal.to(torch.int64).argmax(0)              # first minimal plane
         out[s] = torch.gather(cand, 0, first[None, ..., None].expand((1,) + cand.shape[1:]))[0]
     return out
@@ -100,11 +104,11 @@ def state(n_s, I_s, g_s, m):
     return torch.where(v < 0, I_s, v)
 
 
-def edge_states(grid, I, ring=None):
+def edge_states(grid, I, ring=None, tie_rtol=TIE_RTOL):
     """States at every Voronoi edge midpoint from the edge's first and its second
     direction: two tensors [Ne, *cells]."""
     I = torch.as_tensor(I, dtype=F64)
-    g = slopes(grid, I, ring)
+    g = slopes(grid, I, ring, tie_rtol)
     ne = len(grid.edges)
     first = torch.zeros((ne,) + I.shape[1:], dtype=F64)
     second = torch.zeros_like(first)

@@ -49,7 +49,7 @@ def build_ks(wl, grid=None, limiter=tr.LIM_MC, fd_h=1e-3):
     from .kerr import KerrSchildLogR
     grid = grid or GeodesicGrid(wl["generation"], wl["weights"])
     geo = KerrSchildLogR(wl["n"], wl["xlo"], wl["xhi"], grid, wl["a"], wl.get("M", 1.0), fd_h,
-                         recon=wl.get("angular_recon", "donor"))
+                         recon=wl.get("angular_recon", "donor"), mapr_tie_rtol=wl.get("mapr_tie_rtol"))
     shape = tuple(wl["n"])
     u = np.asarray(wl["u"], dtype=np.float64)
     u_hat = geo.u_hat(u)

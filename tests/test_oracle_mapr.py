@@ -1,4 +1,4 @@
-"""Pins of the oracle's MAPR angular reconstruction (Sec. 3.5, edge states of
+"""Pins of the oracle's MAPR angular reconstruction (Sec. 3.4, edge states of
 the angular fluxes) against properties its reading implies, each computed by
 a route the oracle does not take:
   * cyclic order: consecutive neighbours of a direction share a Delaunay
@@ -126,6 +126,29 @@ def test_ties_are_not_decided_by_rounding(grid):
     assert float((mapr.slopes(grid, J, ring)[s, 0] - want).abs().max()) < 1e-14
     n = grid.n[s]
     assert float(np.cross(P[0], P[1]) @ n) > 0          # counter-clockwise from outside
+
+
+def test_tie_band_of_the_fp32_form(grid):
+    """The FP32 form counts planes within 1e-4 (relative |g|^2) of the
+    flattest as tied, the FP64 form within 1e-8: break the pole's five-fold
+    symmetry so that the third pair plane is flatter by a relative 1e-6; the
+    FP64 band takes it, the FP32 band keeps the first plane of the ring."""
+    ring = mapr.rings(grid)
+    s = 0
+    r = ring[s]
+    P = mapr.gnomonic(grid.n[s], grid.n[r])
+    J = torch.zeros((grid.ns, 1), dtype=F64)
+    J[s] = 1.0
+    # neighbours 2 and 3 (the third pair) rise a little: that plane flattens
+    J[r[2]] = J[r[3]] = 5e-7
+    cand = [mapr.pair_slope(P[k], P[(k + 1) % 5], J[r[k]] - 1.0, J[r[(k + 1) % 5]] - 1.0)[0]
+            for k in range(5)]
+    norms = [float(c @ c) for c in cand]
+    assert min(norms) == norms[2] and 1e-8 < (norms[0] - norms[2]) / norms[2] < 1e-4
+    g64 = mapr.slopes(grid, J, ring)[s, 0]
+    g32 = mapr.slopes(grid, J, ring, tie_rtol=mapr.TIE_RTOL_FP32)[s, 0]
+    assert float((g64 - cand[2]).abs().max()) < 1e-15
+    assert float((g32 - cand[0]).abs().max()) < 1e-15
 
 
 def test_positivity_fallback(grid):
