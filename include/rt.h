@@ -173,6 +173,25 @@ rt_status rt_set_opacities(rt_ctx* ctx, const rt_opacity_desc* desc, hipStream_t
 rt_status rt_step(rt_ctx* ctx, void* I, double* T, double dt, int nsteps, double* G_out,
                   double* R_out, hipStream_t stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+   capture, tight serving loops, harnesses that forbid hipMalloc): rt_step with
+   the same arguments, semantics and results, whose step scratch (the
+   half-step intensity, the lazy interaction maps, the half-step temperature,
+   and in curved space the angular divergence and the MAPR slopes) lives in a
+   static device array of 64 MiB per device instead of context allocations.
+   The call allocates nothing and records no kernel timing events; the tile
+   launch order of the stage kernels is the context's cached one when it was
+   built by an earlier rt_step call, else the natural order (same results).
+   Every call on one device shares that array and leaves it holding its last
+   contents: calls that overlap on one device (two streams, two threads, two
+   contexts) race and must be serialised by the caller.  Errors: RT_E_ARG as
+   rt_step, and when the grid needs more than 64 MiB of step scratch
+   (about Nc * (Ns * elem + 56) bytes flat, plus Ns * Nc * elem curved and
+   2 Ns * Nc * elem more with MAPR); RT_E_STATE when the array's device address
+   could not be resolved at rt_init_grid. */
+rt_status rt_step_noalloc(rt_ctx* ctx, void* I, double* T, double dt, int nsteps, double* G_out,
+                          double* R_out, hipStream_t stream);
+
 /* Moments (Eq. R): R[k][c] = sum_s w_s n^a n^b I[s][c] for the 10 pairs
    (a,b) = 00,01,02,03,11,12,13,22,23,33 (n^0 = 1), accumulated in FP64.
    frame RT_COORD returns e^mu_a e^nu_b R^(ab) instead (identity when flat;

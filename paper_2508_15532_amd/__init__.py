@@ -145,6 +145,16 @@ class RTContext:
                                _ptr(R, "R", torch.float64, 10 * self.nc, optional=True), _stream())
         return N.check(st, allow_warning=True)
 
+    def step_noalloc(self, I, T, dt, nsteps=1, G=None, R=None):
+        """As step(), through rt_step_noalloc: the step scratch is the library's
+        static per-device array (no device allocation in the call)."""
+        import torch
+        st = self._lib.rt_step_noalloc(self._ctx, _ptr(I, "I", self.intensity_dtype, self.ns * self.nc),
+                                       _ptr(T, "T", torch.float64, self.nc), float(dt), int(nsteps),
+                                       _ptr(G, "G", torch.float64, 4 * self.nc, optional=True),
+                                       _ptr(R, "R", torch.float64, 10 * self.nc, optional=True), _stream())
+        return N.check(st, allow_warning=True)
+
     def moments(self, I, R=None, J=None, frame="tetrad"):
         """R [10, *n] float64 (00,01,02,03,11,12,13,22,23,33) of I; optional J [*n]."""
         import torch

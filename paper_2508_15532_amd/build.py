@@ -7,6 +7,7 @@ import os
 import shutil
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
@@ -18,7 +19,8 @@ COMMON = ["-O3", "-fPIC", "-std=c++17", f"--offload-arch={ARCH}",
           # packed FP32 VALU ops stay disabled (hand-checked scalar/float2 code only)
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-I", os.path.join(ROOT, "include"), "-Wall", "-Wno-unused-result"]
-SOURCES = ["grid.cpp", "kerr.cpp", "api.cpp", "kernels.hip", "stage.hip", "angular.hip", "adjoint.hip"]
+SOURCES = ["grid.cpp", "kerr.cpp", "api.cpp", "kernels.hip", "stage.hip", "angular.hip", "adjoint.hip",
+           "noalloc.hip"]
 
 
 def hipcc():
@@ -32,15 +34,21 @@ def build(verbose=False):
     cc = hipcc()
     objdir = os.path.join(PKG, "_build")
     os.makedirs(objdir, exist_ok=True)
-    objs = []
+    cmds, objs = [], []
     for src in SOURCES:
         obj = os.path.join(objdir, os.path.splitext(src)[0] + ".o")
         lang = ["-x", "hip"] if src.endswith(".hip") else []
-        cmd = [cc] + COMMON + lang + ["-c", os.path.join(CSRC, src), "-o", obj]
+        cmds.append([cc] + COMMON + lang + ["-c", os.path.join(CSRC, src), "-o", obj])
+        objs.append(obj)
+
+    def compile_one(cmd):
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.run(cmd, check=True)
-        objs.append(obj)
+
+    # the sources compile independently; at most 8 at a time
+    with ThreadPoolExecutor(max_workers=min(8, os.cpu_count() or 1)) as pool:
+        list(pool.map(compile_one, cmds))
     tmp = LIB + ".tmp"
     cmd = [cc, "-shared", f"--offload-arch={ARCH}", "-o", tmp] + objs
     if verbose:

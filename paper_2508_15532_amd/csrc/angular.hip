@@ -162,12 +162,12 @@ k_angular_patch(long long nc, int n3, int ns, long long nruns, const S* __restri
 }
 
 template <typename S>
-hipError_t launch_cw(rt_ctx* c, const void* I, hipStream_t st) {
+hipError_t launch_cw(rt_ctx* c, const void* I, void* angD, hipStream_t st) {
   const long long nrt = (long long)c->n[0] * c->n[1];
   const int cw = c->ks_cw;
   const dim3 grid((unsigned)(nrt * ((c->n[2] + cw - 1) / cw))), block(256);
   const S* in = (const S*)I;
-  S* out = (S*)c->d_angD;
+  S* out = (S*)angD;
   const S* A = (const S*)c->d_acoef;
   if (!c->ks_lco) {
     constexpr int PCW = 256 / (int)sizeof(S);  // 256-byte rows
@@ -295,33 +295,34 @@ k_mapr_flux(long long nc, int n3, int ns, const S* __restrict__ I, const S* __re
 }
 
 template <typename S>
-hipError_t launch_mapr(rt_ctx* c, const void* I, hipStream_t st) {
+hipError_t launch_mapr(rt_ctx* c, const void* I, void* angD, void* grad, hipStream_t st) {
   const long long chunks8 = ((c->nc + 255) / 256 + 7) / 8 * 8;
   const long long nblk = chunks8 * c->ns;
   if (nblk > 0xffffffffLL) return hipErrorInvalidConfiguration;
   const dim3 grid((unsigned)nblk), block(256);
   const S* in = (const S*)I;
-  S* G = (S*)c->d_mp_grad;
+  S* G = (S*)grad;
   hipLaunchKernelGGL((k_mapr_slope<S>), grid, block, 0, st, c->nc, c->ns, in, G, c->d_mp_ring,
                      (const S*)c->d_mp_minv);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (c->n[2] % 64 == 0)
     hipLaunchKernelGGL((k_mapr_flux<S, true>), grid, block, 0, st, c->nc, c->n[2], c->ns, in,
-                       (const S*)G, (S*)c->d_angD, c->d_inc, (const S*)c->d_mp_pq,
+                       (const S*)G, (S*)angD, c->d_inc, (const S*)c->d_mp_pq,
                        (const S*)c->d_mp_coef, c->d_mp_self);
   else
     hipLaunchKernelGGL((k_mapr_flux<S, false>), grid, block, 0, st, c->nc, c->n[2], c->ns, in,
-                       (const S*)G, (S*)c->d_angD, c->d_inc, (const S*)c->d_mp_pq,
+                       (const S*)G, (S*)angD, c->d_inc, (const S*)c->d_mp_pq,
                        (const S*)c->d_mp_coef, c->d_mp_self);
   return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t launch_angular(rt_ctx* c, const void* I, hipStream_t st) {
-  if (c->mapr) return c->fp32 ? launch_mapr<float>(c, I, st) : launch_mapr<double>(c, I, st);
-  return c->fp32 ? launch_cw<float>(c, I, st) : launch_cw<double>(c, I, st);
+hipError_t launch_angular(rt_ctx* c, const void* I, void* angD, void* grad, hipStream_t st) {
+  if (c->mapr)
+    return c->fp32 ? launch_mapr<float>(c, I, angD, grad, st) : launch_mapr<double>(c, I, angD, grad, st);
+  return c->fp32 ? launch_cw<float>(c, I, angD, st) : launch_cw<double>(c, I, angD, st);
 }
 
 }  // namespace rt

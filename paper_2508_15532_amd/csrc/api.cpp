@@ -359,6 +359,175 @@ rt_status set_kerr_schild(rt_ctx* c, double M, double a, double cfl) {
   return RT_OK;
 }
 }  // namespace
+
+namespace {
+size_t round256(size_t b) { return (b + 255) / 256 * 256; }
+}  // namespace
+
+size_t step_scratch_bytes(const rt_ctx* c) {
+  const size_t nc = (size_t)c->nc, ns = (size_t)c->ns;
+  size_t b = round256(ns * nc * c->elem) + 2 * round256(3 * nc * 8) + round256(nc * 8);
+  if (c->curved) b += round256(ns * nc * c->elem);
+  if (c->mapr) b += round256(2 * ns * nc * c->elem);
+  return b;
+}
+
+StepScratch carve_step_scratch(const rt_ctx* c, void* base) {
+  const size_t nc = (size_t)c->nc, ns = (size_t)c->ns;
+  char* q = (char*)base;
+  auto take = [&](size_t bytes) -> void* {
+    void* r = q;
+    q += round256(bytes);
+    return r;
+  };
+  StepScratch w{};
+  w.Itil = take(ns * nc * c->elem);
+  w.mapA = (double*)take(3 * nc * 8);
+  w.mapB = (double*)take(3 * nc * 8);
+  w.Tstar = (double*)take(nc * 8);
+  w.angD = c->curved ? take(ns * nc * c->elem) : nullptr;
+  w.mp_grad = c->mapr ? take(2 * ns * nc * c->elem) : nullptr;
+  return w;
+}
+
+namespace {
+// The steps of rt_step on a given scratch.  may_alloc = false: nothing is
+// allocated (no kernel timing events, no new tile order).
+rt_status step_impl(rt_ctx* c, const StepScratch& ws, bool may_alloc, void* I, double* T, double dt,
+                    int nsteps, double* G_out, double* R_out, hipStream_t stream) {
+  StageArgs a{};
+  a.n1 = c->n[0];
+  a.n2 = c->n[1];
+  a.n3 = c->n[2];
+  a.nc = c->nc;
+  a.ns = c->ns;
+  for (int ax = 0; ax < 3; ++ax) {
+    a.bc_lo[ax] = c->desc.bc_lo[ax];
+    a.bc_hi[ax] = c->desc.bc_hi[ax];
+    a.inv_dx[ax] = 1.0 / c->dx[ax];
+  }
+  a.dt = dt;
+  a.abar = c->desc.abar;
+  a.limiter = c->desc.limiter;
+  a.model = c->opac.model;
+  a.gamma = c->opac.gamma;
+  a.C_a = c->opac.C_a;
+  a.C_s = c->opac.C_s;
+  a.rho_floor = c->desc.rho_floor;
+  a.max_iter = c->opac.newton_max_iter;
+  a.rtol = c->opac.newton_rtol;
+  a.W0 = c->W0;
+  for (int k = 0; k < 10; ++k) a.Wsum[k] = c->Wsum[k];
+  a.curved = c->curved ? 1 : 0;
+  a.zin_stride = c->ks_zin_stride;
+  a.pole_rows = c->desc.pole_zero_rows;
+  StagePtrs p{};
+  p.rho = c->d_rho;
+  p.ka = c->d_ka;
+  p.ks = c->d_ks;
+  p.jv = c->d_j;
+  p.uhat = c->d_uhat;
+  p.vel = c->d_v;
+  p.dirF_v = c->fp32 ? (const void*)c->d_dir_f : (const void*)c->d_dir;
+  p.dirD = c->d_dir;
+  p.w = c->d_w;
+  p.W16 = c->d_W16;
+  p.fail = c->d_count;
+  if (c->curved) {
+    p.rec_r_v = c->d_rec_r;
+    p.rec_t_v = c->d_rec_t;
+    p.rec_p_v = c->d_rec_p;
+    p.zin = c->d_zin;
+    p.angD_v = ws.angD;
+    p.nu0 = c->d_nu0;
+  }
+  // kernel timing creates events: only where the call may allocate
+  auto run = [&](int kind, auto&& launch) -> hipError_t {
+    return may_alloc ? timed(c, kind, stream, launch) : launch();
+  };
+  const double* mapA = nullptr;  // the caller's I is materialised on entry
+  for (int k = 0; k < nsteps; ++k) {
+    const bool last = k == nsteps - 1;
+    // stage 1: fluxes of I^n, half step, interaction from T^n with opacities at T^n
+    a.h = 0.5 * dt;
+    p.Iflux_v = I;
+    p.mapF = mapA;
+    p.Ibase_v = nullptr;
+    p.mapB = nullptr;
+    p.Iout_v = ws.Itil;
+    p.mapO = ws.mapB;
+    p.Tstart = T;
+    p.Tcoef = T;
+    p.Tout = ws.Tstar;
+    if (c->curved)
+      RT_HIP(run(RT_K_ANGULAR, [&] { return launch_angular(c, I, ws.angD, ws.mp_grad, stream); }));
+    RT_HIP(run(RT_K_STAGE1, [&] { return launch_stage(c, a, p, false, stream, may_alloc); }));
+    const double* mapB = ws.mapB;
+    if (c->moving) {
+      RT_HIP(run(RT_K_MATERIALIZE, [&] {
+        return launch_materialize(c, ws.Itil, ws.mapB, a.h, nullptr, nullptr, stream);
+      }));
+      mapB = nullptr;
+    }
+    // stage 2: fluxes of I*, full step from I^n, energy balance from T^n, opacities at T*
+    a.h = dt;
+    p.Iflux_v = ws.Itil;
+    p.mapF = mapB;
+    p.Ibase_v = I;
+    p.mapB = mapA;
+    p.Iout_v = I;
+    p.mapO = ws.mapA;
+    p.Tstart = T;
+    p.Tcoef = ws.Tstar;
+    p.Tout = T;
+    if (c->curved)
+      RT_HIP(run(RT_K_ANGULAR, [&] { return launch_angular(c, ws.Itil, ws.angD, ws.mp_grad, stream); }));
+    RT_HIP(run(RT_K_STAGE2, [&] { return launch_stage(c, a, p, true, stream, may_alloc); }));
+    if (c->moving) {
+      RT_HIP(run(RT_K_MATERIALIZE, [&] {
+        return launch_materialize(c, I, ws.mapA, dt, last ? R_out : nullptr, last ? G_out : nullptr,
+                                  stream);
+      }));
+      mapA = nullptr;
+    } else {
+      mapA = ws.mapA;
+    }
+  }
+  if (mapA) {
+    // at rest the last interaction is still a lazy map: apply it, with the
+    // moments and the 4-force of the last step
+    RT_HIP(run(RT_K_MATERIALIZE, [&] { return launch_materialize(c, I, mapA, dt, R_out, G_out, stream); }));
+  }
+  if (c->debug & 1) {
+    RT_HIP(launch_nonfinite(c, I, T, stream));
+    unsigned long long h[2];
+    RT_HIP(hipMemcpyAsync(h, c->d_count, sizeof h, hipMemcpyDeviceToHost, stream));
+    RT_HIP(hipStreamSynchronize(stream));
+    RT_HIP(launch_fill_u64(c->d_count + 1, 1, 0ull, stream));
+    if (h[1]) return fail(RT_E_NONFINITE, "rt_step: " + std::to_string(h[1]) + " non-finite values");
+    if (h[0]) {
+      set_error("rt_step: " + std::to_string(h[0]) + " cells without a valid temperature root");
+      return RT_W_NEWTON;
+    }
+  }
+  return RT_OK;
+}
+
+// argument checks shared by rt_step and rt_step_noalloc
+rt_status check_step_args(const rt_ctx* c, const char* who, const void* I, const double* T, double dt,
+                          int nsteps, const double* G_out, const double* R_out) {
+  const std::string w(who);
+  if (!c) return fail(RT_E_ARG, w + ": ctx is NULL");
+  if (!c->metric_set || !c->opac_set) return fail(RT_E_STATE, w + ": set metric and opacities first");
+  if (!I || !T) return fail(RT_E_ARG, w + ": I and T are required");
+  if (!aligned(I) || !aligned(T) || (G_out && !aligned(G_out)) || (R_out && !aligned(R_out)))
+    return fail(RT_E_ARG, w + ": arrays must be 256-byte aligned");
+  if (nsteps < 0) return fail(RT_E_ARG, w + ": nsteps must be >= 0");
+  if (!(dt > 0.0) || dt > c->dt_max * (1.0 + 1e-12))
+    return fail(RT_E_ARG, w + ": need 0 < dt <= dt_max (" + std::to_string(c->dt_max) + ")");
+  return RT_OK;
+}
+}  // namespace
 }  // namespace rt
 
 using namespace rt;
@@ -423,6 +592,13 @@ rt_status rt_init_grid(const rt_grid_desc* d, rt_ctx** out) {
   if (e != hipSuccess) {
     delete c;
     return hip_fail(e, "hipGetDevice");
+  }
+  // the allocation-free entry point's static scratch: its address on this
+  // device, resolved once per device with the device current (a failure here
+  // only disables rt_step_noalloc, which then reports it)
+  if ((e = noalloc_scratch_init(c->device)) != hipSuccess) {
+    c->noalloc_error = std::string("hipGetSymbolAddress of the static scratch: ") + hipGetErrorString(e);
+    (void)hipGetLastError();
   }
   const int ns = c->ns;
   const int ns4 = (ns + 3) / 4 * 4;
@@ -572,130 +748,34 @@ rt_status rt_set_opacities(rt_ctx* c, const rt_opacity_desc* o, hipStream_t stre
 
 rt_status rt_step(rt_ctx* c, void* I, double* T, double dt, int nsteps, double* G_out,
                   double* R_out, hipStream_t stream) {
-  if (!c) return fail(RT_E_ARG, "rt_step: ctx is NULL");
-  if (!c->metric_set || !c->opac_set) return fail(RT_E_STATE, "rt_step: set metric and opacities first");
-  if (!I || !T) return fail(RT_E_ARG, "rt_step: I and T are required");
-  if (!aligned(I) || !aligned(T) || (G_out && !aligned(G_out)) || (R_out && !aligned(R_out)))
-    return fail(RT_E_ARG, "rt_step: arrays must be 256-byte aligned");
-  if (nsteps < 0) return fail(RT_E_ARG, "rt_step: nsteps must be >= 0");
-  if (!(dt > 0.0) || dt > c->dt_max * (1.0 + 1e-12))
-    return fail(RT_E_ARG, "rt_step: need 0 < dt <= dt_max (" + std::to_string(c->dt_max) + ")");
-  rt_status st = use_device(c);
+  rt_status st = check_step_args(c, "rt_step", I, T, dt, nsteps, G_out, R_out);
   if (st) return st;
-  StageArgs a{};
-  a.n1 = c->n[0];
-  a.n2 = c->n[1];
-  a.n3 = c->n[2];
-  a.nc = c->nc;
-  a.ns = c->ns;
-  for (int ax = 0; ax < 3; ++ax) {
-    a.bc_lo[ax] = c->desc.bc_lo[ax];
-    a.bc_hi[ax] = c->desc.bc_hi[ax];
-    a.inv_dx[ax] = 1.0 / c->dx[ax];
-  }
-  a.dt = dt;
-  a.abar = c->desc.abar;
-  a.limiter = c->desc.limiter;
-  a.model = c->opac.model;
-  a.gamma = c->opac.gamma;
-  a.C_a = c->opac.C_a;
-  a.C_s = c->opac.C_s;
-  a.rho_floor = c->desc.rho_floor;
-  a.max_iter = c->opac.newton_max_iter;
-  a.rtol = c->opac.newton_rtol;
-  a.W0 = c->W0;
-  for (int k = 0; k < 10; ++k) a.Wsum[k] = c->Wsum[k];
-  a.curved = c->curved ? 1 : 0;
-  a.zin_stride = c->ks_zin_stride;
-  a.pole_rows = c->desc.pole_zero_rows;
-  StagePtrs p{};
-  p.rho = c->d_rho;
-  p.ka = c->d_ka;
-  p.ks = c->d_ks;
-  p.jv = c->d_j;
-  p.uhat = c->d_uhat;
-  p.vel = c->d_v;
-  p.dirF_v = c->fp32 ? (const void*)c->d_dir_f : (const void*)c->d_dir;
-  p.dirD = c->d_dir;
-  p.w = c->d_w;
-  p.W16 = c->d_W16;
-  p.fail = c->d_count;
-  if (c->curved) {
-    p.rec_r_v = c->d_rec_r;
-    p.rec_t_v = c->d_rec_t;
-    p.rec_p_v = c->d_rec_p;
-    p.zin = c->d_zin;
-    p.angD_v = c->d_angD;
-    p.nu0 = c->d_nu0;
-  }
-  const double* mapA = nullptr;  // the caller's I is materialised on entry
-  for (int k = 0; k < nsteps; ++k) {
-    const bool last = k == nsteps - 1;
-    // stage 1: fluxes of I^n, half step, interaction from T^n with opacities at T^n
-    a.h = 0.5 * dt;
-    p.Iflux_v = I;
-    p.mapF = mapA;
-    p.Ibase_v = nullptr;
-    p.mapB = nullptr;
-    p.Iout_v = c->d_Itil;
-    p.mapO = c->d_mapB;
-    p.Tstart = T;
-    p.Tcoef = T;
-    p.Tout = c->d_Tstar;
-    if (c->curved)
-      RT_HIP(timed(c, RT_K_ANGULAR, stream, [&] { return launch_angular(c, I, stream); }));
-    RT_HIP(timed(c, RT_K_STAGE1, stream, [&] { return launch_stage(c, a, p, false, stream); }));
-    const double* mapB = c->d_mapB;
-    if (c->moving) {
-      RT_HIP(timed(c, RT_K_MATERIALIZE, stream, [&] {
-        return launch_materialize(c, c->d_Itil, c->d_mapB, a.h, nullptr, nullptr, stream);
-      }));
-      mapB = nullptr;
-    }
-    // stage 2: fluxes of I*, full step from I^n, energy balance from T^n, opacities at T*
-    a.h = dt;
-    p.Iflux_v = c->d_Itil;
-    p.mapF = mapB;
-    p.Ibase_v = I;
-    p.mapB = mapA;
-    p.Iout_v = I;
-    p.mapO = c->d_mapA;
-    p.Tstart = T;
-    p.Tcoef = c->d_Tstar;
-    p.Tout = T;
-    if (c->curved)
-      RT_HIP(timed(c, RT_K_ANGULAR, stream, [&] { return launch_angular(c, c->d_Itil, stream); }));
-    RT_HIP(timed(c, RT_K_STAGE2, stream, [&] { return launch_stage(c, a, p, true, stream); }));
-    if (c->moving) {
-      RT_HIP(timed(c, RT_K_MATERIALIZE, stream, [&] {
-        return launch_materialize(c, I, c->d_mapA, dt, last ? R_out : nullptr, last ? G_out : nullptr,
-                                  stream);
-      }));
-      mapA = nullptr;
-    } else {
-      mapA = c->d_mapA;
-    }
-  }
-  if (mapA) {
-    // at rest the last interaction is still a lazy map: apply it, with the
-    // moments and the 4-force of the last step
-    RT_HIP(timed(c, RT_K_MATERIALIZE, stream, [&] {
-      return launch_materialize(c, I, mapA, dt, R_out, G_out, stream);
-    }));
-  }
-  if (c->debug & 1) {
-    RT_HIP(launch_nonfinite(c, I, T, stream));
-    unsigned long long h[2];
-    RT_HIP(hipMemcpyAsync(h, c->d_count, sizeof h, hipMemcpyDeviceToHost, stream));
-    RT_HIP(hipStreamSynchronize(stream));
-    RT_HIP(hipMemsetAsync(c->d_count + 1, 0, sizeof(unsigned long long), stream));
-    if (h[1]) return fail(RT_E_NONFINITE, "rt_step: " + std::to_string(h[1]) + " non-finite values");
-    if (h[0]) {
-      set_error("rt_step: " + std::to_string(h[0]) + " cells without a valid temperature root");
-      return RT_W_NEWTON;
-    }
-  }
-  return RT_OK;
+  if ((st = use_device(c))) return st;
+  StepScratch ws{};
+  ws.Itil = c->d_Itil;
+  ws.mapA = c->d_mapA;
+  ws.mapB = c->d_mapB;
+  ws.Tstar = c->d_Tstar;
+  ws.angD = c->d_angD;
+  ws.mp_grad = c->d_mp_grad;
+  return step_impl(c, ws, true, I, T, dt, nsteps, G_out, R_out, stream);
+}
+
+rt_status rt_step_noalloc(rt_ctx* c, void* I, double* T, double dt, int nsteps, double* G_out,
+                          double* R_out, hipStream_t stream) {
+  rt_status st = check_step_args(c, "rt_step_noalloc", I, T, dt, nsteps, G_out, R_out);
+  if (st) return st;
+  const size_t need = step_scratch_bytes(c);
+  if (need > kNoallocScratchBytes)
+    return fail(RT_E_ARG, "rt_step_noalloc: this grid needs " + std::to_string(need) +
+                              " bytes of step scratch; the static scratch holds " +
+                              std::to_string(kNoallocScratchBytes));
+  if ((st = use_device(c))) return st;
+  void* base = noalloc_scratch_ptr(c->device);
+  if (!base)
+    return fail(RT_E_STATE, "rt_step_noalloc: the static scratch of this device is not resolved (" +
+                                c->noalloc_error + ")");
+  return step_impl(c, carve_step_scratch(c, base), false, I, T, dt, nsteps, G_out, R_out, stream);
 }
 
 rt_status rt_moments(rt_ctx* c, const void* I, double* R, double* J, int frame, hipStream_t stream) {

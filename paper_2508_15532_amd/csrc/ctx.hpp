@@ -89,6 +89,7 @@ struct rt_ctx {
   unsigned* d_tile_order = nullptr;
   long long tile_order_key = -1;
   int debug = 0;
+  std::string noalloc_error;  // why the static scratch could not be resolved, if it could not
   // kernel timing (debug bit 1): events recorded around launches
   struct Timed {
     int kind;
@@ -114,6 +115,34 @@ inline size_t angular_lds_bytes(int ns, int cw, size_t elem, bool lco) {
 }
 
 void set_error(const std::string& msg);
+
+// Device scratch of one rt_step call: the half-step intensity (stage-1
+// output), the two lazy interaction maps, the half-step temperature and, in
+// curved space, the angular flux divergence and the MAPR slopes.  rt_step takes
+// them from the context's own allocations; the allocation-free entry point
+// carves them from the library's static scratch array.
+struct StepScratch {
+  void* Itil;       // [ns][nc] transport type
+  double* mapA;     // [3][nc]
+  double* mapB;     // [3][nc]
+  double* Tstar;    // [nc]
+  void* angD;       // [ns][nc] transport type (curved only, else NULL)
+  void* mp_grad;    // [ns][2][nc] transport type (MAPR only, else NULL)
+};
+// bytes of a context's step scratch laid out as 256-byte aligned parts, and
+// that layout carved from one base pointer
+size_t step_scratch_bytes(const rt_ctx* c);
+StepScratch carve_step_scratch(const rt_ctx* c, void* base);
+
+// The allocation-free entry point's scratch (noalloc.hip): a file-scope static
+// device array of kNoallocScratchBytes, one per device, held until the process
+// ends.  noalloc_scratch_init resolves its device address once per device (the
+// device must be current) and must run before noalloc_scratch_ptr returns it.
+constexpr size_t kNoallocScratchBytes = size_t(64) << 20;
+hipError_t noalloc_scratch_init(int device);
+void* noalloc_scratch_ptr(int device);
+// n 64-bit words at p set to v, by a kernel (no memset node in a captured graph)
+hipError_t launch_fill_u64(unsigned long long* p, int n, unsigned long long v, hipStream_t st);
 
 // all launchers enqueue on `st` and return the launch status
 hipError_t launch_fluid(rt_ctx* c, const double* u, hipStream_t st);

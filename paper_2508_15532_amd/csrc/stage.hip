@@ -916,11 +916,12 @@ namespace {
 // tiles stage the same direction at about the same time) instead of HBM.
 // The order is a permutation of the tiles; codes pack (tx, ty, tz).
 hipError_t tile_order(rt_ctx* c, int tx, int ty, int tz, int TYc, int TZc, int resident,
-                      const unsigned** out) {
+                      bool may_alloc, const unsigned** out) {
   *out = nullptr;
   if (tx > 1024 || ty > 2048 || tz > 2048) return hipSuccess;  // natural order
   const long long key = (((long long)tx * 4096 + ty) * 4096 + tz) * 64 * 64 +
                         (long long)(TYc * 8 + TZc) * 64 + std::min(resident, 63);
+  if (key != c->tile_order_key && !may_alloc) return hipSuccess;  // natural order, nothing allocated
   if (key != c->tile_order_key) {
     int dev = 0, cus = 256;
     if (hipGetDevice(&dev) == hipSuccess)
@@ -963,13 +964,13 @@ hipError_t tile_order(rt_ctx* c, int tx, int ty, int tz, int TYc, int TZc, int r
 
 template <typename Kern>
 hipError_t launch_ordered(rt_ctx* c, Kern kern, StageArgs a, StagePtrs p, int TYc, int TZc,
-                          hipStream_t st) {
+                          hipStream_t st, bool may_alloc) {
   int resident = 1;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&resident, reinterpret_cast<const void*>(kern),
                                                    TX * TYc, 0) != hipSuccess)
     resident = 1;
   hipError_t e = tile_order(c, a.tiles_x, a.tiles_y, a.tiles_z, TYc, TZc, std::max(resident, 1),
-                            &p.tile_order);
+                            may_alloc, &p.tile_order);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(kern, dim3(8 * a.tiles_per_xcd), dim3(TX * TYc), 0, st, a, p);
   return hipGetLastError();
@@ -977,7 +978,8 @@ hipError_t launch_ordered(rt_ctx* c, Kern kern, StageArgs a, StagePtrs p, int TY
 
 // MOVE: the moving-fluid family (moving fluid or curved geometry), else at rest
 template <typename S, typename F, int TZ, int LIM, bool MOVE>
-hipError_t launch_tiled(rt_ctx* c, StageArgs a, const StagePtrs& p, bool stage2, hipStream_t st) {
+hipError_t launch_tiled(rt_ctx* c, StageArgs a, const StagePtrs& p, bool stage2, hipStream_t st,
+                        bool ma) {
   constexpr int TY = !MOVE ? 8 : 4;  // as in k_stage
   a.tiles_x = (c->n[2] + TX - 1) / TX;
   a.tiles_y = (c->n[1] + TY - 1) / TY;
@@ -987,36 +989,36 @@ hipError_t launch_tiled(rt_ctx* c, StageArgs a, const StagePtrs& p, bool stage2,
   if constexpr (MOVE) {
     if (c->curved) {
       // curved geometry always runs the moving-fluid form (direction-dependent map)
-      return stage2 ? launch_ordered(c, k_stage<S, F, TZ, true, true, LIM, true>, a, p, TY, TZ, st)
-                    : launch_ordered(c, k_stage<S, F, TZ, false, true, LIM, true>, a, p, TY, TZ, st);
+      return stage2 ? launch_ordered(c, k_stage<S, F, TZ, true, true, LIM, true>, a, p, TY, TZ, st, ma)
+                    : launch_ordered(c, k_stage<S, F, TZ, false, true, LIM, true>, a, p, TY, TZ, st, ma);
     }
-    return stage2 ? launch_ordered(c, k_stage<S, F, TZ, true, true, LIM, false>, a, p, TY, TZ, st)
-                  : launch_ordered(c, k_stage<S, F, TZ, false, true, LIM, false>, a, p, TY, TZ, st);
+    return stage2 ? launch_ordered(c, k_stage<S, F, TZ, true, true, LIM, false>, a, p, TY, TZ, st, ma)
+                  : launch_ordered(c, k_stage<S, F, TZ, false, true, LIM, false>, a, p, TY, TZ, st, ma);
   } else {
-    return stage2 ? launch_ordered(c, k_stage<S, F, TZ, true, false, LIM, false>, a, p, TY, TZ, st)
-                  : launch_ordered(c, k_stage<S, F, TZ, false, false, LIM, false>, a, p, TY, TZ, st);
+    return stage2 ? launch_ordered(c, k_stage<S, F, TZ, true, false, LIM, false>, a, p, TY, TZ, st, ma)
+                  : launch_ordered(c, k_stage<S, F, TZ, false, false, LIM, false>, a, p, TY, TZ, st, ma);
   }
 }
 }  // namespace
 
 hipError_t launch_stage(rt_ctx* c, const StageArgs& a, const StagePtrs& p, bool stage2,
-                        hipStream_t st) {
+                        hipStream_t st, bool may_alloc) {
   const bool mc = a.limiter == RT_LIM_MC;
   // the moving-fluid and curved forms carry more per-cell state (the fluid
   // velocity, advection weights, records): two cells per column (one in FP64)
   // keep them in registers
   const bool mv = c->moving || c->curved;
   if (c->fp32 && mv)
-    return mc ? launch_tiled<float, float, 2, RT_LIM_MC, true>(c, a, p, stage2, st)
-              : launch_tiled<float, float, 2, RT_LIM_MINMOD, true>(c, a, p, stage2, st);
+    return mc ? launch_tiled<float, float, 2, RT_LIM_MC, true>(c, a, p, stage2, st, may_alloc)
+              : launch_tiled<float, float, 2, RT_LIM_MINMOD, true>(c, a, p, stage2, st, may_alloc);
   if (c->fp32)
-    return mc ? launch_tiled<float, float, 4, RT_LIM_MC, false>(c, a, p, stage2, st)
-              : launch_tiled<float, float, 4, RT_LIM_MINMOD, false>(c, a, p, stage2, st);
+    return mc ? launch_tiled<float, float, 4, RT_LIM_MC, false>(c, a, p, stage2, st, may_alloc)
+              : launch_tiled<float, float, 4, RT_LIM_MINMOD, false>(c, a, p, stage2, st, may_alloc);
   if (mv)
-    return mc ? launch_tiled<double, double, 1, RT_LIM_MC, true>(c, a, p, stage2, st)
-              : launch_tiled<double, double, 1, RT_LIM_MINMOD, true>(c, a, p, stage2, st);
-  return mc ? launch_tiled<double, double, 2, RT_LIM_MC, false>(c, a, p, stage2, st)
-            : launch_tiled<double, double, 2, RT_LIM_MINMOD, false>(c, a, p, stage2, st);
+    return mc ? launch_tiled<double, double, 1, RT_LIM_MC, true>(c, a, p, stage2, st, may_alloc)
+              : launch_tiled<double, double, 1, RT_LIM_MINMOD, true>(c, a, p, stage2, st, may_alloc);
+  return mc ? launch_tiled<double, double, 2, RT_LIM_MC, false>(c, a, p, stage2, st, may_alloc)
+            : launch_tiled<double, double, 2, RT_LIM_MINMOD, false>(c, a, p, stage2, st, may_alloc);
 }
 
 hipError_t launch_materialize(rt_ctx* c, void* I, const double* map, double h, double* R,

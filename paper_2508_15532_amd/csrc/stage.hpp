@@ -66,11 +66,14 @@ struct StagePtrs {
   const unsigned* tile_order;
 };
 
+// may_alloc = false: the call allocates nothing (the tile launch order is taken
+// from the context's cache when it matches, else tiles run in natural order)
 hipError_t launch_stage(rt_ctx* c, const StageArgs& a, const StagePtrs& p, bool stage2,
-                        hipStream_t st);
+                        hipStream_t st, bool may_alloc = true);
 hipError_t launch_materialize(rt_ctx* c, void* I, const double* map, double h, double* R,
                               double* G, hipStream_t st);
-// angular flux divergence of I (curved geometry) into c->d_angD
-hipError_t launch_angular(rt_ctx* c, const void* I, hipStream_t st);
+// angular flux divergence of I (curved geometry) into angD; MAPR keeps its
+// per-direction slopes in grad ([ns][2][nc])
+hipError_t launch_angular(rt_ctx* c, const void* I, void* angD, void* grad, hipStream_t st);
 
 }  // namespace rt
