@@ -44,7 +44,10 @@ typedef struct rt_ctx rt_ctx;
 typedef enum {
   RT_OK = 0,
   RT_W_NEWTON = 1,      /* step done; some cells had no valid temperature root
-                           and kept their pre-interaction state (debug mode) */
+                           and kept their pre-interaction state.  Returned only
+                           with debug checking on (rt_set_debug bit 0): without
+                           it rt_step returns before the device has run, so the
+                           count is read with rt_newton_failures instead */
   RT_E_ARG = -1,        /* invalid argument (null pointer, size, enum, dt) */
   RT_E_STATE = -2,      /* call order violated (e.g. step before set_metric) */
   RT_E_HIP = -3,        /* a HIP runtime call failed */
@@ -64,7 +67,7 @@ enum { RT_FP64 = 0, RT_FP32_TRANSPORT = 1 };
 /* PLI slope limiter (Sec. 3.4) */
 enum { RT_LIM_MC = 0, RT_LIM_MINMOD = 1 };
 /* states at the Voronoi edges for the angular fluxes of the curved geometry
-   (Sec. 3.5): the upwind direction's own intensity (donor cell), or its MAPR
+   (Sec. 3.5; reconstruction of Sec. 3.4): the upwind direction's own intensity (donor cell), or its MAPR
    reconstruction: the flattest of the planes through the direction and
    consecutive pairs of its neighbours in gnomonic coordinates, evaluated at
    the edge midpoint and replaced by the cell value where negative */
@@ -168,7 +171,10 @@ rt_status rt_set_opacities(rt_ctx* ctx, const rt_opacity_desc* desc, hipStream_t
          step's second interaction, -(R^(0a)(after) - R^(0a)(before))/dt.
    R_out optional [10][Nc]: moments (as rt_moments, tetrad frame, FP64 sums of
          the stored intensity) of the intensity returned, i.e. of the last
-         step; computed in the pass that applies the last interaction.
+         step; computed in the pass that applies the last interaction, where
+         the intensity is already in registers (an argument added to the
+         step for that reason: it saves the separate read of I that
+         rt_moments would make).
    0 < dt <= dt_max of rt_set_metric, else RT_E_ARG. */
 rt_status rt_step(rt_ctx* ctx, void* I, double* T, double dt, int nsteps, double* G_out,
                   double* R_out, hipStream_t stream);
@@ -224,7 +230,10 @@ enum { RT_K_STAGE1 = 0, RT_K_STAGE2, RT_K_MATERIALIZE, RT_K_MOMENTS, RT_K_ADJOIN
        RT_K_ANGULAR /* curved: angular flux divergence before each stage */, RT_NKERNELS };
 rt_status rt_kernel_times(rt_ctx* ctx, int* counts, double* ms);
 
-/* Number of interaction failures counted since the last call (debug mode). */
+/* Number of cells whose interaction found no valid temperature root (they
+   kept their pre-interaction state), counted by every rt_step and
+   rt_step_noalloc since the previous call of this function; synchronises the
+   device. */
 rt_status rt_newton_failures(rt_ctx* ctx, long long* count);
 
 void rt_destroy(rt_ctx* ctx);

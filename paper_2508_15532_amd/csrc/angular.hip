@@ -193,7 +193,7 @@ hipError_t launch_cw(rt_ctx* c, const void* I, void* angD, hipStream_t st) {
   return hipGetLastError();
 }
 
-// MAPR edge states (Sec. 3.5).  Pass 1: per direction s and cell, the slope of
+// MAPR edge states (Sec. 3.4; used by the angular fluxes of Sec. 3.5).  Pass 1: per direction s and cell, the slope of
 // the flattest plane through (0, I_s) and a consecutive pair (a, b) of the
 // neighbours in the gnomonic coordinates of s:
 //   g = Minv_(s,ab) (I_a - I_s, I_b - I_s).

@@ -119,7 +119,7 @@ rt_status upload(T** dst, const std::vector<T>& v) {
   return RT_OK;
 }
 
-// MAPR tables (Sec. 3.5, angular edge states).  Per direction s, with an
+// MAPR tables (Sec. 3.4, angular edge states of the Sec. 3.5 fluxes).  Per direction s, with an
 // orthonormal basis (e1, e2) of its tangent plane, a point x has the gnomonic
 // coordinates of p = x / (x . n_s) - n_s.  The neighbours of s, sorted by the
 // angle of their coordinates (counter-clockwise seen from outside, from the
