@@ -39,6 +39,48 @@ k_moments(long long nc, int ns, const S* __restrict__ I, const double* __restric
   d4 acc[4];
   for (int m = 0; m < 4; ++m) acc[m] = d4{0.0, 0.0, 0.0, 0.0};
   if constexpr (sizeof(S) == 4) {
+    if (cell0 + 64 <= nc && (nc & 3) == 0) {
+      // FP32 intensities, whole wave of cells: lane (r, kq) loads the four
+      // consecutive cells cell0 + 4r .. 4r + 3 of direction s0 + kq in one
+      // 16-byte load, component m being row r of tile m (tile m's row i is
+      // cell cell0 + 4i + m); batches of B four-direction steps, all loads of
+      // a batch issued before its products
+      constexpr int B = 4;
+      const float* base = (const float*)I + cell0 + 4 * r;
+      for (int s00 = 0; s00 < ns; s00 += 4 * B) {
+        float4 av[B];
+        double b[B];
+#pragma unroll
+        for (int u = 0; u < B; ++u) {
+          const int s = s00 + 4 * u + kq;
+          b[u] = s < ns ? W16[s * 16 + r] : 0.0;
+          av[u] = s < ns ? *reinterpret_cast<const float4*>(base + (long long)s * nc)
+                         : float4{0.f, 0.f, 0.f, 0.f};
+        }
+#pragma unroll
+        for (int u = 0; u < B; ++u) {
+          acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64((double)av[u].x, b[u], acc[0], 0, 0, 0);
+          acc[1] = __builtin_amdgcn_mfma_f64_16x16x4f64((double)av[u].y, b[u], acc[1], 0, 0, 0);
+          acc[2] = __builtin_amdgcn_mfma_f64_16x16x4f64((double)av[u].z, b[u], acc[2], 0, 0, 0);
+          acc[3] = __builtin_amdgcn_mfma_f64_16x16x4f64((double)av[u].w, b[u], acc[3], 0, 0, 0);
+        }
+      }
+      // D[i][j] of tile m sits in lane j + 16 (i % 4), element i / 4: lane (r, kq)
+      // holds component r of cells cell0 + 4 (4e + kq) + m, m = 0..3 contiguous
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const long long cc = cell0 + 16 * e + 4 * kq;
+        if (r < 10) {
+          double* o = R + (long long)r * nc + cc;
+          *reinterpret_cast<d4*>(o) = d4{acc[0][e], acc[1][e], acc[2][e], acc[3][e]};
+        }
+        if (J && r == 0) {
+          const double q = 1.0 / (4.0 * kPi);
+          *reinterpret_cast<d4*>(J + cc) = d4{acc[0][e] * q, acc[1][e] * q, acc[2][e] * q, acc[3][e] * q};
+        }
+      }
+      return;
+    }
     for (int s0 = 0; s0 < ns; s0 += 4) {
       const int s = s0 + kq;
       const double b = W16[s * 16 + r];  // W16 is zero-padded to a multiple of 4 rows
