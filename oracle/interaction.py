@@ -14,22 +14,44 @@ Steps, in the paper's order, for every cell (vectorised over cells):
   4. A1, A2 (Eq. A1, Eq. A2) and Ebar_- (Eq. Ebar_calc);
   5. the temperature equation: Method 1 quartic (Eq. semi_implicit_T) or
      Method 2 (Eq. implicit_T, alpha_P^a = N T_+^(-7/2)), solved by Newton;
-     or a fixed emissivity (S_+ = 4 pi j, T unchanged);
+     Method 3 (Eq. T_almost_fully_implicit, the total opacity semi-implicit),
+     solved by bisection; or a fixed emissivity (S_+ = 4 pi j, T unchanged);
   6. Ebar_+ from the energy balance (Eq. ideal_gas_difference);
-  7. Ibar_+ from Eq. fluid_interaction_discrete, then back to the tetrad
+  7. Ibar_+ from Eq. fluid_interaction_discrete (Method 3: with the factor
+     alpha_-/alpha_+ of its rewritten A1', A2'), then back to the tetrad
      frame, I_+ = Ibar_+ / (nbar^0)^4.
+
+Method 3, as read here.  Writing the implicit update of each direction as
+  Ibar_+ = (1/(alpha dt)) [n^0/(n^0/(alpha dt) + nbar^0)] Ibar_-
+         + (1/(alpha dt)) [nbar^0 dt/(4 pi (n^0/(alpha dt) + nbar^0))] S,
+S = alpha_P^a T_+^4 + alpha^s Ebar_+, the method takes alpha_+ = alpha(T_+)
+in the factor outside the brackets and alpha_- = alpha(T_coef) inside, so the
+angular integrals are those of Methods 1-2 (A1, A2, computed once) and every
+direction's update carries the factor r = alpha_-/alpha_+.  Integrated over
+solid angle: Ebar_+ = r (A1 + A2 S).  With Ebar_+ = E0 - Y T_+
+(Eq. ideal_gas_difference, E0 = Ebar_- + Y T_-) and the bremsstrahlung law
+alpha^a = N T^-7/2 (so alpha_P^a T_+^4 = N sqrt(T_+)), multiplying by
+alpha_+ T_+^3.5 dt gives the printed polynomial
+  -Y alpha^s (dt - B2) T^4.5 - B2 N T^4 - [B2 alpha^s E0 + B1 - E0 alpha^s dt] T^3.5
+  - Y N dt T + E0 N dt = 0
+term by term when its A1', A2' are the bare integrals B1 = alpha_- dt A1,
+B2 = alpha_- dt A2 (as printed, A1' and A2' also carry the prefactor
+1/(alpha_+ dt), which would make the polynomial inconsistent).  The root
+sought is the one with a non-negative gas energy, T_+ in (0, E0/Y), where
+  F(T) = (E0 - Y T)(N T^-3.5 + alpha^s (1 - alpha_- A2)) - alpha_- (A1 + A2 N sqrt T)
+is strictly decreasing from +inf to F(E0/Y) < 0: it is unique.
 """
 import math
 import torch
 
-KIRCHHOFF_CONST, BREMS, FIXED_EMISSIVITY = 0, 1, 2
+KIRCHHOFF_CONST, BREMS, FIXED_EMISSIVITY, BREMS_M3 = 0, 1, 2, 3
 
 
 def opacities(model, rho, T, kappa_a, kappa_s, C_a, C_s, rho_floor):
     """Fluid-frame absorption and scattering coefficients alpha = rho kappa
     (Sec. 3.6.2).  Bremsstrahlung-like model: alpha^a = C_a rho^2 T^-7/2,
     alpha^s = C_s rho.  Zero below the density floor (Sec. 3.8)."""
-    if model == BREMS:
+    if model in (BREMS, BREMS_M3):
         aa = C_a * rho * rho * T.pow(-3.5)
         as_ = C_s * rho
     else:
@@ -58,6 +80,24 @@ def newton_positive_root(a, b, K, p, max_iter=50, rtol=1e-14):
         done = done | (dT.abs() <= rtol * Tn.abs())
         T = Tn
     return T, done
+
+
+def method3_root(Y, E0, Nbar, as_, ab, A1, A2, iters=200):
+    """T_+ of Method 3: the root of F(T) = (E0 - Y T)(N T^-3.5 + alpha^s (1 -
+    alpha_- A2)) - alpha_- (A1 + A2 N sqrt T) in (0, E0/Y), by bisection
+    (F decreases strictly there).  Returns (T, ok)."""
+    ok = (E0 > 0) & (Y > 0) & (Nbar > 0) & (A1 >= 0) & (1.0 - ab * A2 > 0)
+    one = torch.ones_like(E0)
+    hi = torch.where(ok, E0 / torch.where(ok, Y, one), one)
+    lo = torch.zeros_like(hi)
+    for _ in range(iters):
+        mid = 0.5 * (lo + hi)
+        F = ((E0 - Y * mid) * (Nbar * mid.pow(-3.5) + as_ * (1.0 - ab * A2))
+             - ab * (A1 + A2 * Nbar * mid.sqrt()))
+        pos = F > 0
+        lo = torch.where(pos, mid, lo)
+        hi = torch.where(pos, hi, mid)
+    return 0.5 * (lo + hi), ok
 
 
 def interact(It, T_start, T_coef, rho, u_hat, n_up0, nhat, w, h, model,
@@ -90,11 +130,21 @@ def interact(It, T_start, T_coef, rho, u_hat, n_up0, nhat, w, h, model,
     Y = rho / (gamma - 1.0)
     q = 1.0 - A2 * as_
     K = A1 - Y * q * T_start - q * Em
+    r = torch.ones_like(Y)        # alpha_- / alpha_+ (Method 3), else 1
     if model == FIXED_EMISSIVITY:
         Sp = 4.0 * math.pi * j
         Tp = T_start
         Ep = (A1 + A2 * Sp) / q
         ok = torch.ones_like(Tp, dtype=torch.bool)
+    elif model == BREMS_M3:
+        Nbar = C_a * rho * rho
+        E0 = Em + Y * T_start
+        Tp, ok = method3_root(Y, E0, Nbar, as_, ab, A1, A2)
+        Tp = torch.where(ok, Tp, T_start)
+        Sp = torch.where(ok, Nbar * Tp.sqrt(), torch.zeros_like(Tp))
+        Ep = E0 - Y * Tp
+        ab_plus = Nbar * Tp.pow(-3.5) + as_
+        r = torch.where(ok, ab / ab_plus, torch.ones_like(Y))
     else:
         valid = (K < 0) & (q > 0)
         Ks = torch.where(valid, K, -torch.ones_like(K))
@@ -115,7 +165,7 @@ def interact(It, T_start, T_coef, rho, u_hat, n_up0, nhat, w, h, model,
         # 6. energy balance
         Ep = Em - Y * (Tp - T_start)
     # 7. implicit intensity update and return to the tetrad frame
-    Ibp = c * Ib + d * (Sp + as_ * Ep)
+    Ibp = r * (c * Ib + d * (Sp + as_ * Ep))
     Iout = Ibp / nb0.pow(4)
     live = rho >= rho_floor
     use = live & ok
@@ -123,6 +173,6 @@ def interact(It, T_start, T_coef, rho, u_hat, n_up0, nhat, w, h, model,
     Tout = torch.where(use, Tp, T_start)
     failed = live & ~ok
     if diag is not None:
-        diag.update(nb0=nb0, Em=Em, A1=A1, A2=A2, Y=Y, q=q, K=K, Tp=Tp, Sp=Sp, Ep=Ep,
+        diag.update(nb0=nb0, Em=Em, A1=A1, A2=A2, Y=Y, q=q, K=K, Tp=Tp, Sp=Sp, Ep=Ep, r=r,
                     abar_a=aa, abar_s=as_)
     return Iout, Tout, failed

@@ -14,7 +14,7 @@ from .step import Problem
 F64 = torch.float64
 BC = {"periodic": tr.PERIODIC, "outflow": tr.OUTFLOW, "zero_incoming": tr.ZERO_INCOMING}
 MODEL = {"kirchhoff_const": src.KIRCHHOFF_CONST, "brems": src.BREMS,
-         "fixed_emissivity": src.FIXED_EMISSIVITY}
+         "fixed_emissivity": src.FIXED_EMISSIVITY, "brems_m3": src.BREMS_M3}
 
 
 def _t(x):
