@@ -80,8 +80,14 @@ enum { RT_FLAT = 0, RT_KERR_SCHILD = 1 };
    BREMS            alpha^a = C_a rho^2 T^-7/2, alpha^s = C_s rho, Planck
                     opacity implicit in T (Method 2);
    FIXED_EMISSIVITY alpha^a = rho kappa_a, alpha^s = rho kappa_s, emission
-                    4 pi j fixed per cell, temperature unchanged */
-enum { RT_OPAC_KIRCHHOFF_CONST = 0, RT_OPAC_BREMS = 1, RT_OPAC_FIXED_EMISSIVITY = 2 };
+                    4 pi j fixed per cell, temperature unchanged;
+   BREMS_M3         the BREMS opacities with Method 3 (Eq. T_almost_fully_implicit):
+                    the angular integrals use the explicit total opacity
+                    alpha_- = alpha(T_coef), the factor outside them the implicit
+                    alpha_+ = alpha(T_+), so every direction's update carries
+                    alpha_-/alpha_+; T_+ is the root with non-negative gas energy
+                    (safeguarded Newton; at least 120 iterations allowed) */
+enum { RT_OPAC_KIRCHHOFF_CONST = 0, RT_OPAC_BREMS = 1, RT_OPAC_FIXED_EMISSIVITY = 2, RT_OPAC_BREMS_M3 = 3 };
 /* frame of the moments returned by rt_moments */
 enum { RT_TETRAD = 0, RT_COORD = 1 };
 

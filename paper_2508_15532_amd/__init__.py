@@ -14,7 +14,7 @@ from ._native import RTError  # noqa: F401
 _BC = {"periodic": N.RT_BC_PERIODIC, "outflow": N.RT_BC_OUTFLOW,
        "zero_incoming": N.RT_BC_ZERO_INCOMING}
 _MODEL = {"kirchhoff_const": N.RT_OPAC_KIRCHHOFF_CONST, "brems": N.RT_OPAC_BREMS,
-          "fixed_emissivity": N.RT_OPAC_FIXED_EMISSIVITY}
+          "fixed_emissivity": N.RT_OPAC_FIXED_EMISSIVITY, "brems_m3": N.RT_OPAC_BREMS_M3}
 _PREC = {"fp64": N.RT_FP64, "fp32": N.RT_FP32_TRANSPORT}
 
 

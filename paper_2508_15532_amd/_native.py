@@ -20,7 +20,7 @@ RT_FP64, RT_FP32_TRANSPORT = 0, 1
 RT_LIM_MC, RT_LIM_MINMOD = 0, 1
 RT_AREC_DONOR, RT_AREC_MAPR = 0, 1
 RT_FLAT, RT_KERR_SCHILD = 0, 1
-RT_OPAC_KIRCHHOFF_CONST, RT_OPAC_BREMS, RT_OPAC_FIXED_EMISSIVITY = 0, 1, 2
+RT_OPAC_KIRCHHOFF_CONST, RT_OPAC_BREMS, RT_OPAC_FIXED_EMISSIVITY, RT_OPAC_BREMS_M3 = 0, 1, 2, 3
 RT_TETRAD, RT_COORD = 0, 1
 KERNELS = ["stage1", "stage2", "materialize", "moments", "adjoint", "angular"]
 

@@ -708,7 +708,7 @@ rt_status rt_set_metric(rt_ctx* c, int kind, double M, double a, double cfl, dou
 rt_status rt_set_opacities(rt_ctx* c, const rt_opacity_desc* o, hipStream_t stream) {
   if (!c || !o) return fail(RT_E_ARG, "rt_set_opacities: NULL argument");
   if (!c->metric_set) return fail(RT_E_STATE, "rt_set_opacities: call rt_set_metric first");
-  if (o->model < RT_OPAC_KIRCHHOFF_CONST || o->model > RT_OPAC_FIXED_EMISSIVITY)
+  if (o->model < RT_OPAC_KIRCHHOFF_CONST || o->model > RT_OPAC_BREMS_M3)
     return fail(RT_E_ARG, "rt_set_opacities: bad model");
   if (!(o->gamma > 1.0)) return fail(RT_E_ARG, "rt_set_opacities: gamma must be > 1");
   if (!o->rho) return fail(RT_E_ARG, "rt_set_opacities: rho is required");

@@ -92,7 +92,7 @@ __device__ __forceinline__ void opac(const StageArgs& a, const double* __restric
                                      const double* __restrict__ ks, long long c, double& aa,
                                      double& as) {
   double r = rho[c];
-  if (a.model == RT_OPAC_BREMS) {
+  if (a.model == RT_OPAC_BREMS || a.model == RT_OPAC_BREMS_M3) {
     const double t = T[c];
     aa = a.C_a * r * r / (t * t * t * sqrt(t));  // T^-3.5
     as = a.C_s * r;
@@ -136,15 +136,63 @@ __device__ __forceinline__ void face_coefs(double tau, double& P, double& Q, dou
 // Positive root machinery of the temperature equations (Sec. 3.6.2).
 struct Solve {
   double T, Q;  // T_+, and Q = S_+ + alpha^s E_+
+  double r;     // alpha_- / alpha_+ (Method 3), else 1
   bool ok;
 };
+
+// Method 3 (the total opacity semi-implicit): T_+ is the root in (0, E0/Y) of
+//   F(T) = (E0 - Y T)(N T^-3.5 + alpha^s (1 - alpha_- A2)) - alpha_- (A1 + A2 N sqrt T),
+// the energy balance E_+ = E0 - Y T_+ with E_+ = r (A1 + A2 S_+),
+// r = alpha_-/alpha_+, S_+ = N sqrt(T_+).  F decreases strictly and is convex on
+// that interval, so Newton from either side of the root stays in the bracket
+// or is replaced by bisection.
+__device__ bool method3_root(double Y, double E0, double N, double as, double ab, double A1, double A2,
+                             double T0, int max_iter, double rtol, double& T) {
+  const double qs = as * (1.0 - ab * A2);
+  if (!(E0 > 0.0) || !(Y > 0.0) || !(N > 0.0) || !(A1 >= 0.0) || !(1.0 - ab * A2 > 0.0)) return false;
+  double lo = 0.0, hi = E0 / Y;
+  double x = (T0 > 0.0 && T0 < hi) ? T0 : 0.5 * hi;
+  for (int it = 0; it < max_iter; ++it) {
+    const double sx = sqrt(x), ix = 1.0 / x;
+    const double p35 = ix * ix * ix / sx;  // x^-3.5
+    const double g = N * p35 + qs, e = E0 - Y * x;
+    const double F = e * g - ab * (A1 + A2 * N * sx);
+    const double dF = -Y * g - 3.5 * e * N * p35 * ix - 0.5 * ab * A2 * N / sx;
+    if (F > 0.0) lo = x;
+    else hi = x;
+    double xn = x - F / dF;
+    if (!(xn > lo && xn < hi)) xn = 0.5 * (lo + hi);
+    const double dx = xn - x;
+    x = xn;
+    if (fabs(dx) <= rtol * x || hi - lo <= rtol * x) {
+      T = x;
+      return true;
+    }
+  }
+  return false;
+}
 
 __device__ Solve solve_cell(const StageArgs& a, double r, double T0, double aa, double as,
                             double Em, double A1, double A2, double jc) {
   const double Y = r / (a.gamma - 1.0);
   const double q = 1.0 - A2 * as;
   const double K = A1 - Y * q * T0 - q * Em;
-  Solve o{T0, 0.0, true};
+  Solve o{T0, 0.0, 1.0, true};
+  if (a.model == RT_OPAC_BREMS_M3) {
+    const double N = a.C_a * r * r, E0 = Em + Y * T0, ab = aa + as;
+    double Tp = T0;
+    // with the Newton cap of Methods 1-2, at least the bisection depth of FP64
+    if (!method3_root(Y, E0, N, as, ab, A1, A2, T0, max(a.max_iter, 120), a.rtol, Tp)) {
+      o.ok = false;
+      return o;
+    }
+    const double st = sqrt(Tp);
+    const double Ep = E0 - Y * Tp;
+    o.T = Tp;
+    o.Q = N * st + as * Ep;
+    o.r = ab / (N / (Tp * Tp * Tp * st) + as);
+    return o;
+  }
   if (a.model == RT_OPAC_FIXED_EMISSIVITY) {
     double Sp = 4.0 * kPi * jc;
     double Ep = (A1 + A2 * Sp) / q;
@@ -717,7 +765,7 @@ k_stage(StageArgs a, StagePtrs p) {
       A1 = cs * Em;
       A2 = a.h / (4.0 * kPi * (1.0 + ab * a.h)) * a.W0;
     }
-    Solve so{T0k, 0.0, false};
+    Solve so{T0k, 0.0, 1.0, false};
     if (live) {
       so = solve_cell(a, rrk, T0k, aak, ask, Em, A1, A2, p.jv ? p.jv[c] : 0.0);
       if (!so.ok && p.fail) atomicAdd(p.fail, 1ull);
@@ -728,13 +776,14 @@ k_stage(StageArgs a, StagePtrs p) {
       // parameters of the direction-dependent map, applied by the materialisation
       p.mapO[c] = use ? so.Q : 0.0;
       p.mapO[nc + c] = ab;
-      // 1: apply the interaction, 0: keep I~, 2: zero (rows next to the axis)
+      // > 0: apply the interaction times this factor (alpha_-/alpha_+ in
+      // Method 3, else 1), 0: keep I~, < 0: zero (rows next to the axis)
       const int gyk = (int)((c / n3) % n2);
       const bool pole = CURVED && (gyk < a.pole_rows || gyk >= n2 - a.pole_rows);
-      p.mapO[2 * nc + c] = pole ? 2.0 : (use ? 1.0 : 0.0);
+      p.mapO[2 * nc + c] = pole ? -1.0 : (use ? so.r : 0.0);
     } else {
-      const double al = use ? 1.0 / (1.0 + ab * a.h) : 1.0;
-      const double be = use ? a.h * so.Q / (4.0 * kPi * (1.0 + ab * a.h)) : 0.0;
+      const double al = use ? so.r / (1.0 + ab * a.h) : 1.0;
+      const double be = use ? so.r * a.h * so.Q / (4.0 * kPi * (1.0 + ab * a.h)) : 0.0;
       p.mapO[c] = al;
       p.mapO[nc + c] = be;
     }
@@ -790,8 +839,8 @@ k_materialize(long long nc, int ns, double h, const double* __restrict__ map, S*
     return;
   }
   const double Q = map[c], ab = map[nc + c];
-  const double code = map[2 * nc + c];  // 1: apply, 0: keep, 2: zero
-  const bool use = code == 1.0, zero = code == 2.0;
+  const double code = map[2 * nc + c];  // > 0: apply times code, 0: keep, < 0: zero
+  const bool use = code > 0.0, zero = code < 0.0;
   const double n0c = nu0 ? nu0[c / n3] : 1.0;
   const double u0 = uhat[c], u1 = uhat[nc + c], u2 = uhat[2 * nc + c], u3 = uhat[3 * nc + c];
   const double hQ = h / (4.0 * kPi) * Q;
@@ -816,7 +865,7 @@ k_materialize(long long nc, int ns, double h, const double* __restrict__ map, S*
         // den = n^0 + nb abar h, as one division
         const double nb = u0 - (u1 * dirD[s] + u2 * dirD[ns + s] + u3 * dirD[2 * ns + s]);
         const double nb3 = nb * nb * nb;
-        Io = (n0c * nb3 * It + hQ) / ((n0c + nb * ab * h) * nb3);
+        Io = code * (n0c * nb3 * It + hQ) / ((n0c + nb * ab * h) * nb3);
         *q = (S)Io;
       } else if (zero) {
         Io = 0.0;

@@ -88,6 +88,21 @@ def test_ks_torus_reduced(precision):
         _check_fp32(g, o)
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_ks_torus_method3(precision):
+    """The torus with Method 3 (12x16x8, generation 1, 3 steps, Keplerian flow:
+    the direction-dependent map carries alpha_-/alpha_+)."""
+    wl, I0 = _case()
+    wl["model"] = "brems_m3"
+    _say(f"torus_ks method 3 {precision} 12x16x8 g1 3 steps")
+    g = gpu_run(wl, 3, precision=precision, I0=I0)
+    o = oracle_run(wl, 3, I0=I0)
+    if precision == "fp64":
+        _check_fp64(g, o, wl)
+    else:
+        _check_fp32(g, o)
+
+
 def test_ks_inside_horizon_sign_rule_and_cut():
     """Inner boundary inside the horizon (r_in = 1.2 < r_+ = 1.436 for a = 0.9):
     n_0 changes sign between cells and falls below the cut for some

@@ -66,6 +66,27 @@ def test_brems_reduced(precision):
         _check_fp32(g, o)
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_brems_method3_reduced(precision):
+    """Method 3 on the bremsstrahlung recipe, ragged 10x9x12 periodic box,
+    generation 2, 5 steps; and a stiff variant (density x 6, T x 0.3: alpha dt
+    up to ~1e4) where the semi-implicit opacity matters."""
+    for stiff in (False, True):
+        wl = W.brems_flat(n=(10, 9, 12))
+        wl["model"] = "brems_m3"
+        if stiff:
+            wl["rho"] = wl["rho"] * 6.0
+            wl["T"] = wl["T"] * 0.3
+        _say(f"brems_m3 {precision} 10x9x12 g2 5 steps stiff={stiff}")
+        g = gpu_run(wl, 5, precision=precision)
+        o = oracle_run(wl, 5)
+        assert o["failed"] == 0
+        if precision == "fp64":
+            _check_fp64(g, o)
+        else:
+            _check_fp32(g, o)
+
+
 CASES = [
     # model, bc, limiter, moving, floor, weights
     ("kirchhoff_const", ("periodic",) * 3, "mc", False, False, "voronoi"),
@@ -74,6 +95,9 @@ CASES = [
     ("brems", ("periodic", "periodic", "outflow"), "mc", True, True, "voronoi"),
     ("fixed_emissivity", ("zero_incoming",) * 3, "mc", False, False, "voronoi"),
     ("fixed_emissivity", ("periodic", "outflow", "zero_incoming"), "minmod", True, True, "equal"),
+    # Method 3 (total opacity semi-implicit)
+    ("brems_m3", ("periodic",) * 3, "mc", False, False, "voronoi"),
+    ("brems_m3", ("outflow", "zero_incoming", "periodic"), "minmod", True, True, "voronoi"),
 ]
 
 
