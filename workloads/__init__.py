@@ -162,3 +162,31 @@ def torus_ks(n=(256, 128, 64), a=0.9, generation=2, sigma_ln=None, scattering=Fa
         rho=rho, T=np.ones(shape), kappa_a=None, kappa_s=None, j=None, u=u,
         I0_iso=np.zeros(shape), cfl=0.4, steps=50, pole_rows=4, n0_cut=0.1,
     )
+
+
+def bright_sphere(n=(32, 12, 4), r_in=1.0, r_out=12.0, r_src=2.0, kappa=5.0, generation=1):
+    """Flat space in spherical coordinates (x1 = ln r, theta, phi; M = 0): an
+    opaque ball r < r_src (fixed emissivity j = kappa / (4 pi) per unit
+    density, absorption kappa, so the intensity inside tends to
+    I_s = 1 / (4 pi)) in vacuum out to r_out (density below the floor);
+    inner boundary outflow, outer boundary zero-incoming, phi periodic.
+    The steady state outside the ball is the field of a uniformly bright
+    sphere, J(r) = (I_s / 2) (1 - sqrt(1 - R^2 / r^2)), R the ball's radius."""
+    shape = tuple(int(v) for v in n)
+    xlo = (math.log(r_in), 0.0, 0.0)
+    xhi = (math.log(r_out), math.pi, 2.0 * math.pi)
+    x1 = xlo[0] + (np.arange(shape[0]) + 0.5) * (xhi[0] - xlo[0]) / shape[0]
+    r = np.exp(x1)[:, None, None] * np.ones(shape)
+    src = r < r_src
+    u = np.zeros((4,) + shape)
+    u[0] = 1.0
+    return dict(
+        name="bright_sphere", n=shape, xlo=xlo, xhi=xhi, coords="logr_theta_phi", metric="kerr_schild",
+        a=0.0, M=0.0, generation=generation, weights="voronoi",
+        bc=("outflow", "outflow", "periodic"), bc_hi=("zero_incoming", "outflow", "periodic"),
+        model="fixed_emissivity", gamma=5.0 / 3.0, C_a=1.0, C_s=0.0,
+        rho=np.where(src, 1.0, 1e-6), T=np.ones(shape), kappa_a=np.where(src, kappa, 0.0),
+        kappa_s=np.zeros(shape), j=np.where(src, kappa / (4.0 * math.pi), 0.0), u=u,
+        I0_iso=np.zeros(shape), cfl=0.4, pole_rows=0, n0_cut=0.1,
+        r_src_face=float(np.exp(xlo[0] + np.count_nonzero(src[:, 0, 0]) * (xhi[0] - xlo[0]) / shape[0])),
+    )
