@@ -77,8 +77,9 @@ enum { RT_FLAT = 0, RT_KERR_SCHILD = 1 };
 /* opacity / emission model (Sec. 3.6.2):
    KIRCHHOFF_CONST  alpha^a = rho kappa_a, alpha^s = rho kappa_s, Kirchhoff
                     emission with a constant Planck opacity (Method 1 quartic);
-   BREMS            alpha^a = C_a rho^2 T^-7/2, alpha^s = C_s rho, Planck
-                    opacity implicit in T (Method 2);
+   BREMS            alpha^a = C_a rho^2 T^-7/2 (times kappa_a, a per-cell
+                    dimensionless factor, when given), alpha^s = C_s rho,
+                    Planck opacity implicit in T (Method 2);
    FIXED_EMISSIVITY alpha^a = rho kappa_a, alpha^s = rho kappa_s, emission
                     4 pi j fixed per cell, temperature unchanged;
    BREMS_M3         the BREMS opacities with Method 3 (Eq. T_almost_fully_implicit):
@@ -118,7 +119,8 @@ typedef struct {
   const double* rho;   /* [Nc] mass density (required) */
   const double* u;     /* [4][Nc] coordinate-frame fluid 4-velocity u^mu; NULL: at rest
                           (flat), the normal observer (Kerr-Schild) */
-  const double* kappa_a; /* [Nc] absorption opacity (KIRCHHOFF_CONST, FIXED_EMISSIVITY); NULL: 0 */
+  const double* kappa_a; /* [Nc] absorption opacity (KIRCHHOFF_CONST, FIXED_EMISSIVITY; NULL: 0),
+                            or the factor of the bremsstrahlung opacity (BREMS, BREMS_M3; NULL: 1) */
   const double* kappa_s; /* [Nc] scattering opacity; NULL: 0 */
   const double* j;     /* [Nc] fluid-frame gray emissivity (FIXED_EMISSIVITY); NULL: 0 */
   int newton_max_iter; /* cap of the temperature Newton iteration (>= 1); 50 */
@@ -221,6 +223,21 @@ rt_status rt_moments(rt_ctx* ctx, const void* I, double* R, double* J, int frame
 rt_status rt_step_adjoint(rt_ctx* ctx, const void* I_n, const double* T_n, double dt,
                           const void* gI_np1, void* gI_n, double* g_kappa_a, double* g_j,
                           hipStream_t stream);
+
+/* Adjoint of one rt_step step (nsteps = 1) for the BREMS model (Method 2,
+   Eq. implicit_T; temperature-dependent opacities), flat metric, fluid at
+   rest (other configurations return RT_E_ARG).  Given I^n, T^n and the loss
+   gradients gI_np1 = dL/dI^(n+1) and gT_np1 = dL/dT^(n+1) ([Nc]; NULL: 0),
+   writes gI_n = dL/dI^n (may alias gI_np1) and gT_n = dL/dT^n ([Nc]; may
+   alias neither T_n nor gT_np1), and ADDS dL/dkappa_a of this step into
+   g_kappa_a ([Nc], may be NULL; kappa_a being the per-cell factor of the
+   bremsstrahlung opacity, 1 where the context has none).  The temperature
+   solve is differentiated by the implicit-function theorem; T^n enters
+   through both stages' energy balances and stage 1's opacities, the
+   half-step temperature through stage 2's opacities and optical depths. */
+rt_status rt_step_adjoint_thermal(rt_ctx* ctx, const void* I_n, const double* T_n, double dt,
+                                  const void* gI_np1, const double* gT_np1, void* gI_n, double* gT_n,
+                                  double* g_kappa_a, hipStream_t stream);
 
 /* Debug checking: flags bit 0 -> after each rt_step, synchronise the stream,
    count cells without a valid temperature root (RT_W_NEWTON) and check

@@ -49,10 +49,11 @@ KIRCHHOFF_CONST, BREMS, FIXED_EMISSIVITY, BREMS_M3 = 0, 1, 2, 3
 
 def opacities(model, rho, T, kappa_a, kappa_s, C_a, C_s, rho_floor):
     """Fluid-frame absorption and scattering coefficients alpha = rho kappa
-    (Sec. 3.6.2).  Bremsstrahlung-like model: alpha^a = C_a rho^2 T^-7/2,
-    alpha^s = C_s rho.  Zero below the density floor (Sec. 3.8)."""
+    (Sec. 3.6.2).  Bremsstrahlung-like model: alpha^a = C_a rho^2 T^-7/2 times
+    kappa_a, a per-cell dimensionless factor (1 when not given), alpha^s =
+    C_s rho.  Zero below the density floor (Sec. 3.8)."""
     if model in (BREMS, BREMS_M3):
-        aa = C_a * rho * rho * T.pow(-3.5)
+        aa = C_a * rho * rho * T.pow(-3.5) * kappa_a
         as_ = C_s * rho
     else:
         aa = rho * kappa_a
@@ -137,7 +138,7 @@ def interact(It, T_start, T_coef, rho, u_hat, n_up0, nhat, w, h, model,
         Ep = (A1 + A2 * Sp) / q
         ok = torch.ones_like(Tp, dtype=torch.bool)
     elif model == BREMS_M3:
-        Nbar = C_a * rho * rho
+        Nbar = C_a * rho * rho * kappa_a
         E0 = Em + Y * T_start
         Tp, ok = method3_root(Y, E0, Nbar, as_, ab, A1, A2)
         Tp = torch.where(ok, Tp, T_start)
@@ -151,7 +152,7 @@ def interact(It, T_start, T_coef, rho, u_hat, n_up0, nhat, w, h, model,
         b = Y * q
         if model == BREMS:
             # Method 2: A2 N sqrt(T) + Y q T + K = 0, Newton in y = sqrt(T)
-            Nbar = C_a * rho * rho
+            Nbar = C_a * rho * rho * kappa_a
             y, conv = newton_positive_root(b, A2 * Nbar, Ks, 2.0, max_iter, rtol)
             Tp = y * y
             Sp = Nbar * y

@@ -56,11 +56,18 @@ class Problem:
     def zeros(self):
         return torch.zeros_like(self.rho)
 
+    def kappa_default(self):
+        """kappa_a when none is given: the bremsstrahlung factor defaults to 1,
+        the absorption opacity of the other models to 0."""
+        if self.model in (src.BREMS, src.BREMS_M3):
+            return torch.ones_like(self.rho)
+        return self.zeros()
+
 
 def effective_opacity(pb, T):
     """Direction-independent tetrad-frame opacity alpha-hat = u-hat^0 alpha-bar used
     in tau (Sec. 3.5), evaluated at temperature T; zero below the density floor."""
-    ka = pb.kappa_a if pb.kappa_a is not None else pb.zeros()
+    ka = pb.kappa_a if pb.kappa_a is not None else pb.kappa_default()
     ks = pb.kappa_s if pb.kappa_s is not None else pb.zeros()
     aa, as_ = src.opacities(pb.model, pb.rho, T, ka, ks, pb.C_a, pb.C_s, pb.rho_floor)
     return pb.u_hat[0] * (aa + as_)
@@ -68,7 +75,7 @@ def effective_opacity(pb, T):
 
 def source(pb, It, h, T_start, T_coef):
     g = pb.geo.grid
-    ka = pb.kappa_a if pb.kappa_a is not None else pb.zeros()
+    ka = pb.kappa_a if pb.kappa_a is not None else pb.kappa_default()
     ks = pb.kappa_s if pb.kappa_s is not None else pb.zeros()
     jj = pb.j if pb.j is not None else pb.zeros()
     Iout, Tout, failed = src.interact(

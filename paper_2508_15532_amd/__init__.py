@@ -181,6 +181,22 @@ class RTContext:
             _ptr(g_j, "g_j", torch.float64, self.nc, optional=True), _stream()))
         return gI_n
 
+    def step_adjoint_thermal(self, I_n, T_n, dt, gI_np1, gT_np1=None, gI_n=None, gT_n=None, g_kappa_a=None):
+        """Reverse of one step of the bremsstrahlung model: returns (gI_n, gT_n);
+        accumulates into g_kappa_a (the per-cell opacity factor's gradient)."""
+        import torch
+        if gI_n is None:
+            gI_n = torch.empty_like(gI_np1)
+        if gT_n is None:
+            gT_n = torch.empty_like(T_n)
+        dt_i, f64 = self.intensity_dtype, torch.float64
+        N.check(self._lib.rt_step_adjoint_thermal(
+            self._ctx, _ptr(I_n, "I_n", dt_i, self.ns * self.nc), _ptr(T_n, "T_n", f64, self.nc), float(dt),
+            _ptr(gI_np1, "gI_np1", dt_i, self.ns * self.nc), _ptr(gT_np1, "gT_np1", f64, self.nc, optional=True),
+            _ptr(gI_n, "gI_n", dt_i, self.ns * self.nc), _ptr(gT_n, "gT_n", f64, self.nc),
+            _ptr(g_kappa_a, "g_kappa_a", f64, self.nc, optional=True), _stream()))
+        return gI_n, gT_n
+
     def set_debug(self, flags=1):
         N.check(self._lib.rt_set_debug(self._ctx, int(flags)))
 

@@ -25,7 +25,7 @@ RT_TETRAD, RT_COORD = 0, 1
 KERNELS = ["stage1", "stage2", "materialize", "moments", "adjoint", "angular"]
 
 EXPORTED = ["rt_init_grid", "rt_geodesic_grid", "rt_grid_info", "rt_set_metric", "rt_set_opacities", "rt_step",
-            "rt_step_noalloc", "rt_moments", "rt_step_adjoint", "rt_set_debug", "rt_kernel_times", "rt_newton_failures",
+            "rt_step_noalloc", "rt_moments", "rt_step_adjoint", "rt_step_adjoint_thermal", "rt_set_debug", "rt_kernel_times", "rt_newton_failures",
             "rt_destroy", "rt_last_error"]
 
 
@@ -68,6 +68,7 @@ def load():
         "rt_step_noalloc": ([P, P, P, D, I, P, P, P], I),
         "rt_moments": ([P, P, P, P, I, P], I),
         "rt_step_adjoint": ([P, P, P, D, P, P, P, P, P], I),
+        "rt_step_adjoint_thermal": ([P, P, P, D, P, P, P, P, P, P], I),
         "rt_set_debug": ([P, I], I),
         "rt_kernel_times": ([P, P, P], I),
         "rt_newton_failures": ([P, C.POINTER(C.c_longlong)], I),

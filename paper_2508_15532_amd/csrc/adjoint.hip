@@ -109,6 +109,8 @@ struct AdjArgs {
   int bc_lo[3], bc_hi[3];
   double inv_dx[3];
   double h, dt, abar, rho_floor, W0;
+  int model;               // RT_OPAC_*: FIXED_EMISSIVITY or BREMS
+  double gamma, C_a, C_s;  // BREMS coefficients, adiabatic index
 };
 
 __device__ __forceinline__ void cell_opac(const AdjArgs& a, const double* rho, const double* ka,
@@ -118,6 +120,116 @@ __device__ __forceinline__ void cell_opac(const AdjArgs& a, const double* rho, c
   aa = ka ? r * ka[c] : 0.0;
   as = ks ? r * ks[c] : 0.0;
   if (!(r >= a.rho_floor)) aa = as = 0.0;
+}
+
+// opacities of a cell at the stage's opacity temperature Tc: the bremsstrahlung
+// law alpha^a = C_a rho^2 Tc^-7/2 times the per-cell factor (kappa_a, 1 when
+// absent), alpha^s = C_s rho; otherwise as cell_opac
+__device__ __forceinline__ void cell_opac_T(const AdjArgs& a, const double* rho, const double* ka,
+                                            const double* ks, const double* Tc, long long c, double& r,
+                                            double& aa, double& as) {
+  if (a.model != RT_OPAC_BREMS) {
+    cell_opac(a, rho, ka, ks, c, r, aa, as);
+    return;
+  }
+  r = rho[c];
+  const double t = Tc[c];
+  aa = a.C_a * r * r / (t * t * t * sqrt(t)) * (ka ? ka[c] : 1.0);
+  as = a.C_s * r;
+  if (!(r >= a.rho_floor)) aa = as = 0.0;
+}
+
+// ---------------------------------------------------------------------------
+// interaction adjoint of the bremsstrahlung model (Method 2) at rest, one
+// thread per cell.  Forward (h = this stage's length, Ts = T_start, Tc = T_coef):
+//   aa = C_a rho^2 Tc^-7/2 m, as = C_s rho, al = 1/(1 + (aa + as) h),
+//   Em = sum_s w_s I~_s, A1 = al Em, A2 = h al W0/(4 pi), Y = rho/(Gamma - 1),
+//   q = 1 - A2 as, K = A1 - Y q Ts - q Em, N = C_a rho^2 m, B = A2 N, b = Y q,
+//   y: b y^2 + B y + K = 0 (y > 0), T+ = y^2, S = N y, E+ = Em - Y (T+ - Ts),
+//   Q = S + as E+, I_out = al I~ + h al Q/(4 pi), T_out = T+
+// (no interaction below the density floor or without a valid root: I_out = I~,
+// T_out = Ts).  Reverse mode of that chain, y by the implicit-function theorem:
+// (2 b y + B) dy = -(y^2 db + y dB + dK).  From gI = dL/dI_out and
+// gTo = dL/dT_out: writes gIt = dL/dI~ (may alias gI), adds dL/dTs to gTs,
+// dL/dTc to gTc and dL/dm to gka (m = kappa_a, the per-cell opacity factor).
+// ---------------------------------------------------------------------------
+template <typename S>
+__global__ void __launch_bounds__(256)
+k_src_adj_brems(AdjArgs a, const S* __restrict__ It, const S* gI, S* gIt, const double* __restrict__ gTo,
+                const double* __restrict__ Ts, const double* __restrict__ Tc, double* gTs, double* gTc,
+                const double* __restrict__ rho, const double* __restrict__ ka,
+                const double* __restrict__ w, double* __restrict__ gka) {
+  const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= a.nc) return;
+  const double r = rho[c], m = ka ? ka[c] : 1.0, tc = Tc[c], ts = Ts[c];
+  const double gT = gTo ? gTo[c] : 0.0;
+  const double h = a.h, k4 = 1.0 / (4.0 * kPi);
+  auto passthrough = [&]() {
+    for (int s = 0; s < a.ns; ++s) gIt[(long long)s * a.nc + c] = gI[(long long)s * a.nc + c];
+    gTs[c] += gT;
+  };
+  if (!(r >= a.rho_floor)) {
+    passthrough();
+    return;
+  }
+  const double aam = a.C_a * r * r / (tc * tc * tc * sqrt(tc));  // d aa / d m
+  const double aa = aam * m, as = a.C_s * r, ab = aa + as;
+  const double al = 1.0 / (1.0 + ab * h);
+  double Em = 0.0, G = 0.0, GI = 0.0;
+  for (int s = 0; s < a.ns; ++s) {
+    const double x = (double)It[(long long)s * a.nc + c], g = (double)gI[(long long)s * a.nc + c];
+    Em += w[s] * x;
+    G += g;
+    GI += g * x;
+  }
+  const double A1 = al * Em, A2 = h * al * a.W0 * k4;
+  const double Y = r / (a.gamma - 1.0), q = 1.0 - A2 * as;
+  const double K = A1 - Y * q * ts - q * Em;
+  if (!((K < 0.0) && (q > 0.0))) {
+    passthrough();
+    return;
+  }
+  const double Nm = a.C_a * r * r, N = Nm * m;  // d N / d m = Nm
+  const double B = A2 * N, b = Y * q;
+  const double y = -2.0 * K / (B + sqrt(B * B - 4.0 * b * K));
+  const double Tp = y * y, Sp = N * y, Ep = Em - Y * (Tp - ts), Q = Sp + as * Ep;
+  // reverse
+  double g_al = GI, g_Q = G * h * al * k4;
+  g_al += G * h * Q * k4;
+  const double g_Sp = g_Q;
+  double g_as = g_Q * Ep;
+  const double g_Ep = g_Q * as;
+  double g_Em = g_Ep, g_Y = g_Ep * (ts - Tp), g_ts = Y * g_Ep;
+  const double g_Tp = gT - Y * g_Ep;
+  double g_N = g_Sp * y;
+  const double g_y = g_Sp * N + 2.0 * y * g_Tp;
+  const double den = 2.0 * b * y + B;
+  const double g_K = -g_y / den, g_b = -g_y * y * y / den, g_B = -g_y * y / den;
+  double g_A2 = g_B * N;
+  g_N += g_B * A2;
+  g_Y += g_b * q;
+  double g_q = g_b * Y;
+  const double g_A1 = g_K;
+  g_Y -= g_K * q * ts;
+  g_q -= g_K * (Y * ts + Em);
+  g_ts -= g_K * Y * q;
+  g_Em -= g_K * q;
+  g_A2 -= g_q * as;
+  g_as -= g_q * A2;
+  g_al += g_A1 * Em + g_A2 * h * a.W0 * k4;
+  g_Em += g_A1 * al;
+  const double g_ab = -g_al * h * al * al;
+  const double g_aa = g_ab;
+  g_as += g_ab;
+  (void)g_as;  // alpha^s = C_s rho: no gradient requested for rho or C_s
+  (void)g_Y;
+  gTs[c] += g_ts;
+  gTc[c] += g_aa * (-3.5 * aa / tc);
+  if (gka) gka[c] += g_aa * aam + g_N * Nm;
+  for (int s = 0; s < a.ns; ++s) {
+    const long long i = (long long)s * a.nc + c;
+    gIt[i] = (S)(al * (double)gI[i] + g_Em * w[s]);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -182,7 +294,8 @@ template <typename S, int LIM>
 __global__ void __launch_bounds__(256)
 k_tr_adj(AdjArgs a, const S* __restrict__ If, const S* __restrict__ gIt, const S* add0,
          const S* add1, S* out, const double* __restrict__ dir, const double* __restrict__ rho,
-         const double* __restrict__ ka, const double* __restrict__ ks, double* __restrict__ gtau) {
+         const double* __restrict__ ka, const double* __restrict__ ks, const double* __restrict__ Tc,
+         double* __restrict__ gtau) {
   const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= a.nc) return;
   const int n1 = a.n[0], n2 = a.n[1], n3 = a.n[2];
@@ -190,25 +303,50 @@ k_tr_adj(AdjArgs a, const S* __restrict__ If, const S* __restrict__ gIt, const S
   const long long st[3] = {(long long)n2 * n3, n3, 1};
   auto alpha_hat = [&](long long cell) {
     double r, aa, as;
-    cell_opac(a, rho, ka, ks, cell, r, aa, as);
+    cell_opac_T(a, rho, ka, ks, Tc, cell, r, aa, as);
     return aa + as;  // fluid at rest: u-hat^0 = 1
   };
-  // per axis: the faces f = m-1 .. m+2 (lower-face index, f in [0, n]) that can
-  // hold this cell in their stencil, with their weights; the thread owns the
-  // tau-gradient of its lower face (and of face n when it is the last cell)
-  double taug[3][2] = {{0, 0}, {0, 0}, {0, 0}};
-  for (int s = 0; s < a.ns; ++s) {
-    const long long off = (long long)s * a.nc;
-    double acc = 0.0;
-    if (add0) acc += (double)add0[off + c];
-    if (add1) acc += (double)add1[off + c];
-    for (int ax = 0; ax < 3; ++ax) {
-      const int na = ax == 0 ? n1 : (ax == 1 ? n2 : n3);
-      const int m = ii[ax];
-      const bool per = a.bc_lo[ax] == RT_BC_PERIODIC;
+  // Axis by axis: the faces f = m-1 .. m+2 (lower-face index, f in [0, n]) that
+  // can hold this cell in their stencil, their weights (functions of the
+  // direction-independent tau, formed once per face), then all directions.
+  // The first axis writes out (with the additive terms), the others add to it.
+  // The thread owns the tau-gradient of its lower face (and of face n when it
+  // is the last cell of a non-periodic axis).
+  for (int ax = 0; ax < 3; ++ax) {
+    const int na = ax == 0 ? n1 : (ax == 1 ? n2 : n3);
+    const int m = ii[ax];
+    const bool per = a.bc_lo[ax] == RT_BC_PERIODIC;
+    const long long base = c - (long long)m * st[ax];
+    const int nfaces = per ? na : na + 1;
+    int fl[4];
+    Wts W[4];
+    int nf = 0;
+    for (int k = -1; k <= 2; ++k) {
+      int f = m + k;
+      if (per) f = wrapc(f, na, true);
+      if (f < 0 || f >= nfaces) continue;
+      bool dup = false;
+      for (int u = 0; u < nf; ++u) dup |= fl[u] == f;
+      if (dup) continue;
+      // the face between cells f-1 and f (stencil positions f-2 .. f+1, wrapped
+      // or clamped on use)
+      const long long cl = base + (long long)wrapc(f - 1, na, per) * st[ax];
+      const long long cr = base + (long long)wrapc(f, na, per) * st[ax];
+      W[nf] = weights(a.abar * 0.5 * (alpha_hat(cl) + alpha_hat(cr)) * a.dt);
+      fl[nf++] = f;
+    }
+    double taug0 = 0.0, taug1 = 0.0;
+    for (int s = 0; s < a.ns; ++s) {
+      const long long off = (long long)s * a.nc;
+      double acc = 0.0;
+      if (ax == 0) {
+        if (add0) acc += (double)add0[off + c];
+        if (add1) acc += (double)add1[off + c];
+      } else {
+        acc = (double)out[off + c];
+      }
       const double nu = dir[ax * a.ns + s];
       const bool pos = nu > 0.0;
-      const long long base = c - (long long)m * st[ax];
       // forward value at (possibly ghost) position p along the axis
       auto val = [&](int p) -> double {
         if (!per) {
@@ -229,31 +367,15 @@ k_tr_adj(AdjArgs a, const S* __restrict__ If, const S* __restrict__ gIt, const S
         if (!per && (p < 0 || p >= na)) return 0.0;
         return (double)gIt[off + base + (long long)wrapc(p, na, per) * st[ax]];
       };
-      const int nfaces = per ? na : na + 1;
-      int seen[4];
-      int nseen = 0;
-      for (int k = -1; k <= 2; ++k) {
-        int f = m + k;
-        if (per) f = wrapc(f, na, true);
-        if (f < 0 || f >= nfaces) continue;
-        bool dup = false;
-        for (int u = 0; u < nseen; ++u) dup |= seen[u] == f;
-        if (dup) continue;
-        seen[nseen++] = f;
-        // stencil positions of face f (between cells f-1 and f); for periodic
-        // axes use the unwrapped positions nearest to m
-        const int p0 = f - 2;  // stencil positions p0 .. p0+3 (wrapped or clamped on use)
-        const double v0 = val(p0), v1 = val(p0 + 1), v2 = val(p0 + 2), v3 = val(p0 + 3);
+      for (int u = 0; u < nf; ++u) {
+        const int p0 = fl[u] - 2;  // stencil positions p0 .. p0+3
         const int L = p0 + 1, R = p0 + 2;  // cells either side of the face
         const double gF = (gcell(R) - gcell(L)) * a.inv_dx[ax] * a.h;
         if (gF == 0.0) continue;
-        // weights of this face
-        const long long cl = base + (long long)wrapc(L, na, per) * st[ax];
-        const long long cr = base + (long long)wrapc(R, na, per) * st[ax];
-        const double tau = a.abar * 0.5 * (alpha_hat(cl) + alpha_hat(cr)) * a.dt;
-        const Wts W = weights(tau);
-        const double cP = pos ? W.P : W.Q, cQ = pos ? W.Q : W.P;
-        const double cU = pos ? W.U2 : W.V2, cV = pos ? W.V2 : W.U2;
+        const double v0 = val(p0), v1 = val(p0 + 1), v2 = val(p0 + 2), v3 = val(p0 + 3);
+        const Wts& Wf = W[u];
+        const double cP = pos ? Wf.P : Wf.Q, cQ = pos ? Wf.Q : Wf.P;
+        const double cU = pos ? Wf.U2 : Wf.V2, cV = pos ? Wf.V2 : Wf.U2;
         double a0, a1, b1, b2;
         const double hL = hslope<LIM>(v1 - v0, v2 - v1, a0, a1);
         const double hR = hslope<LIM>(v2 - v1, v3 - v2, b1, b2);
@@ -270,21 +392,20 @@ k_tr_adj(AdjArgs a, const S* __restrict__ If, const S* __restrict__ gIt, const S
         // F contributes -h F/dx to I~(L) and +h F/dx to I~(R): dL/dF = gF
         acc += gF * contrib;
         // tau-gradient of the faces this thread owns
+        const int f = fl[u];
         const int slot = f == m ? 0 : ((!per && m == na - 1 && f == na) ? 1 : -1);
         if (slot >= 0) {
-          const double dcP = pos ? W.dP : W.dQ, dcQ = pos ? W.dQ : W.dP;
-          const double dcU = pos ? W.dU2 : W.dV2, dcV = pos ? W.dV2 : W.dU2;
+          const double dcP = pos ? Wf.dP : Wf.dQ, dcQ = pos ? Wf.dQ : Wf.dP;
+          const double dcU = pos ? Wf.dU2 : Wf.dV2, dcV = pos ? Wf.dV2 : Wf.dU2;
           const double dFdt = nu * (dcP * v1 + dcQ * v2 + dcU * hL - dcV * hR);
-          taug[ax][slot] += gF * dFdt;
+          (slot == 0 ? taug0 : taug1) += gF * dFdt;
         }
       }
+      out[off + c] = (S)acc;
     }
-    out[off + c] = (S)acc;
-  }
-  // store per-face tau gradients: axis ax, lower face of this cell, and face n
-  for (int ax = 0; ax < 3; ++ax) {
-    gtau[(long long)ax * 2 * a.nc + c] = taug[ax][0];
-    gtau[(long long)ax * 2 * a.nc + a.nc + c] = taug[ax][1];
+    // store per-face tau gradients: axis ax, lower face of this cell, and face n
+    gtau[(long long)ax * 2 * a.nc + c] = taug0;
+    gtau[(long long)ax * 2 * a.nc + a.nc + c] = taug1;
   }
 }
 
@@ -296,7 +417,8 @@ k_tr_adj(AdjArgs a, const S* __restrict__ If, const S* __restrict__ gIt, const S
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(256)
 k_tau_to_kappa(AdjArgs a, const double* __restrict__ gtau, const double* __restrict__ rho,
-               double* __restrict__ gka) {
+               const double* __restrict__ ka, const double* __restrict__ Tc, double* __restrict__ gka,
+               double* __restrict__ gTc) {
   const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= a.nc) return;
   const int n1 = a.n[0], n2 = a.n[1], n3 = a.n[2];
@@ -323,7 +445,17 @@ k_tau_to_kappa(AdjArgs a, const double* __restrict__ gtau, const double* __restr
     if (!per && m == na - 1) g += gu;  // right ghost copies cell n-1
   }
   const double r = rho[c];
-  if (r >= a.rho_floor) gka[c] += r * 0.5 * a.abar * a.dt * g;
+  if (!(r >= a.rho_floor)) return;
+  const double gah = 0.5 * a.abar * a.dt * g;  // dL/dalpha-hat of this cell
+  if (a.model != RT_OPAC_BREMS) {
+    if (gka) gka[c] += r * gah;  // alpha-hat = rho (kappa_a + kappa_s)
+    return;
+  }
+  // alpha-hat = C_a rho^2 Tc^-7/2 m + C_s rho
+  const double t = Tc[c];
+  const double aam = a.C_a * r * r / (t * t * t * sqrt(t));
+  if (gka) gka[c] += aam * gah;
+  gTc[c] += gah * (-3.5 * aam * (ka ? ka[c] : 1.0) / t);
 }
 
 template <typename S>
@@ -341,9 +473,49 @@ k_apply_map(long long nc, int ns, const double* __restrict__ map, const S* __res
 
 }  // namespace
 
+namespace {
+// reverse of one step given the forward states X = I~ (stage 1), Y = I*,
+// Z = I~ (stage 2) and T* (stage 1's temperature); see the kernels above
+template <typename S, int LIM>
+void reverse_step(rt_ctx* c, AdjArgs a, const void* I_n, const double* T_n, const void* X, const void* Y,
+                  const void* Z, const double* Tstar, const void* gI_np1, const double* gT_np1, void* gI_n,
+                  double* gT_n, double* gTstar, double* g_ka, double* g_j, hipStream_t st) {
+  const dim3 grid((unsigned)((c->nc + 255) / 256)), block(256);
+  const bool brems = a.model == RT_OPAC_BREMS;
+  S* gA = (S*)c->d_gA;  // dL/dI~ of stage 2 (also the base contribution to dL/dI^n)
+  S* gB = (S*)c->d_gB;  // dL/dI*, then dL/dI~ of stage 1
+  // stage 2: h = dt, T_start = T^n, T_coef = T*
+  a.h = a.dt;
+  if (brems)
+    hipLaunchKernelGGL(k_src_adj_brems<S>, grid, block, 0, st, a, (const S*)Z, (const S*)gI_np1, gA, gT_np1,
+                       T_n, Tstar, gT_n, gTstar, c->d_rho, c->d_ka, c->d_w, g_ka);
+  else
+    hipLaunchKernelGGL(k_src_adj<S>, grid, block, 0, st, a, (const S*)Z, (const S*)gI_np1, gA, c->d_rho,
+                       c->d_ka, c->d_ks, c->d_j, c->d_w, g_ka, g_j);
+  hipLaunchKernelGGL((k_tr_adj<S, LIM>), grid, block, 0, st, a, (const S*)Y, (const S*)gA, (const S*)nullptr,
+                     (const S*)nullptr, gB, c->d_dir, c->d_rho, c->d_ka, c->d_ks, Tstar, c->d_gcell);
+  if (g_ka || brems)
+    hipLaunchKernelGGL(k_tau_to_kappa, grid, block, 0, st, a, c->d_gcell, c->d_rho, c->d_ka, Tstar, g_ka,
+                       gTstar);
+  // stage 1: h = dt/2, T_start = T_coef = T^n (dL/dT* arrives as dL/dT_out)
+  a.h = 0.5 * a.dt;
+  if (brems)
+    hipLaunchKernelGGL(k_src_adj_brems<S>, grid, block, 0, st, a, (const S*)X, (const S*)gB, gB,
+                       (const double*)gTstar, T_n, T_n, gT_n, gT_n, c->d_rho, c->d_ka, c->d_w, g_ka);
+  else
+    hipLaunchKernelGGL(k_src_adj<S>, grid, block, 0, st, a, (const S*)X, (const S*)gB, gB, c->d_rho, c->d_ka,
+                       c->d_ks, c->d_j, c->d_w, g_ka, g_j);
+  hipLaunchKernelGGL((k_tr_adj<S, LIM>), grid, block, 0, st, a, (const S*)I_n, (const S*)gB, (const S*)gA,
+                     (const S*)gB, (S*)gI_n, c->d_dir, c->d_rho, c->d_ka, c->d_ks, T_n, c->d_gcell);
+  if (g_ka || brems)
+    hipLaunchKernelGGL(k_tau_to_kappa, grid, block, 0, st, a, c->d_gcell, c->d_rho, c->d_ka, T_n, g_ka, gT_n);
+}
+}  // namespace
+
 hipError_t launch_adjoint_step(rt_ctx* c, const void* I_n, const double* T_n, double dt,
-                               const void* gI_np1, void* gI_n, double* g_ka, double* g_j,
-                               hipStream_t st) {
+                               const void* gI_np1, const double* gT_np1, void* gI_n, double* gT_n,
+                               double* g_ka, double* g_j, hipStream_t st) {
+  const bool brems = c->opac.model == RT_OPAC_BREMS;
   // ---- forward recompute: X = I~ of stage 1, Y = I*, Z = I~ of stage 2
   StageArgs sa{};
   sa.n1 = c->n[0];
@@ -380,10 +552,12 @@ hipError_t launch_adjoint_step(rt_ctx* c, const void* I_n, const double* T_n, do
   p.w = c->d_w;
   p.W16 = c->d_W16;
   p.fail = c->d_count;
-  // the temperature is unchanged in this model (T_out goes to scratch)
   void* X = c->d_Itil;
   void* Y = c->d_gC;
   void* Z = c->d_gD;
+  double* Tstar = c->d_Tstar;          // stage 1's temperature (T_coef of stage 2)
+  double* gTstar = c->d_gT;            // dL/dT*
+  double* Tdummy = c->d_gT + c->nc;    // stage 2's temperature, not needed
   sa.h = 0.5 * dt;
   p.Iflux_v = I_n;
   p.mapF = nullptr;
@@ -391,7 +565,7 @@ hipError_t launch_adjoint_step(rt_ctx* c, const void* I_n, const double* T_n, do
   p.mapO = c->d_mapB;
   p.Tstart = T_n;
   p.Tcoef = T_n;
-  p.Tout = c->d_Tstar;
+  p.Tout = Tstar;
   hipError_t e = launch_stage(c, sa, p, false, st);
   if (e != hipSuccess) return e;
   const dim3 grid((unsigned)((c->nc + 255) / 256)), block(256);
@@ -409,6 +583,8 @@ hipError_t launch_adjoint_step(rt_ctx* c, const void* I_n, const double* T_n, do
   p.mapB = nullptr;
   p.Iout_v = Z;
   p.mapO = c->d_mapA;
+  p.Tcoef = brems ? Tstar : T_n;
+  p.Tout = Tdummy;
   e = launch_stage(c, sa, p, true, st);
   if (e != hipSuccess) return e;
 
@@ -426,43 +602,22 @@ hipError_t launch_adjoint_step(rt_ctx* c, const void* I_n, const double* T_n, do
   a.abar = c->desc.abar;
   a.rho_floor = c->desc.rho_floor;
   a.W0 = c->W0;
+  a.model = c->opac.model;
+  a.gamma = c->opac.gamma;
+  a.C_a = c->opac.C_a;
+  a.C_s = c->opac.C_s;
+  if (brems) {
+    if ((e = launch_fill_u64((unsigned long long*)gTstar, (int)c->nc, 0ull, st)) != hipSuccess) return e;
+    if ((e = launch_fill_u64((unsigned long long*)gT_n, (int)c->nc, 0ull, st)) != hipSuccess) return e;
+  }
   const bool mc = c->desc.limiter == RT_LIM_MC;
-  void* gA = c->d_gA;  // dL/dI~ of stage 2 (also the base contribution to dL/dI^n)
-  void* gB = c->d_gB;  // dL/dI*, then dL/dI~ of stage 1
-#define RT_ADJ_LAUNCH(S)                                                                            \
-  do {                                                                                              \
-    a.h = dt;                                                                                       \
-    hipLaunchKernelGGL(k_src_adj<S>, grid, block, 0, st, a, (const S*)Z, (const S*)gI_np1, (S*)gA, \
-                       c->d_rho, c->d_ka, c->d_ks, c->d_j, c->d_w, g_ka, g_j);                     \
-    if (mc)                                                                                         \
-      hipLaunchKernelGGL((k_tr_adj<S, RT_LIM_MC>), grid, block, 0, st, a, (const S*)Y,             \
-                         (const S*)gA, (const S*)nullptr, (const S*)nullptr, (S*)gB, c->d_dir,     \
-                         c->d_rho, c->d_ka, c->d_ks, c->d_gcell);                                  \
-    else                                                                                            \
-      hipLaunchKernelGGL((k_tr_adj<S, RT_LIM_MINMOD>), grid, block, 0, st, a, (const S*)Y,         \
-                         (const S*)gA, (const S*)nullptr, (const S*)nullptr, (S*)gB, c->d_dir,     \
-                         c->d_rho, c->d_ka, c->d_ks, c->d_gcell);                                  \
-    if (g_ka)                                                                                       \
-      hipLaunchKernelGGL(k_tau_to_kappa, grid, block, 0, st, a, c->d_gcell, c->d_rho, g_ka);       \
-    a.h = 0.5 * dt;                                                                                 \
-    hipLaunchKernelGGL(k_src_adj<S>, grid, block, 0, st, a, (const S*)X, (const S*)gB, (S*)gB,     \
-                       c->d_rho, c->d_ka, c->d_ks, c->d_j, c->d_w, g_ka, g_j);                     \
-    if (mc)                                                                                         \
-      hipLaunchKernelGGL((k_tr_adj<S, RT_LIM_MC>), grid, block, 0, st, a, (const S*)I_n,           \
-                         (const S*)gB, (const S*)gA, (const S*)gB, (S*)gI_n, c->d_dir, c->d_rho,   \
-                         c->d_ka, c->d_ks, c->d_gcell);                                            \
-    else                                                                                            \
-      hipLaunchKernelGGL((k_tr_adj<S, RT_LIM_MINMOD>), grid, block, 0, st, a, (const S*)I_n,       \
-                         (const S*)gB, (const S*)gA, (const S*)gB, (S*)gI_n, c->d_dir, c->d_rho,   \
-                         c->d_ka, c->d_ks, c->d_gcell);                                            \
-    if (g_ka)                                                                                       \
-      hipLaunchKernelGGL(k_tau_to_kappa, grid, block, 0, st, a, c->d_gcell, c->d_rho, g_ka);       \
-  } while (0)
-  if (c->fp32)
-    RT_ADJ_LAUNCH(float);
-  else
-    RT_ADJ_LAUNCH(double);
-#undef RT_ADJ_LAUNCH
+  if (c->fp32) {
+    if (mc) reverse_step<float, RT_LIM_MC>(c, a, I_n, T_n, X, Y, Z, Tstar, gI_np1, gT_np1, gI_n, gT_n, gTstar, g_ka, g_j, st);
+    else reverse_step<float, RT_LIM_MINMOD>(c, a, I_n, T_n, X, Y, Z, Tstar, gI_np1, gT_np1, gI_n, gT_n, gTstar, g_ka, g_j, st);
+  } else {
+    if (mc) reverse_step<double, RT_LIM_MC>(c, a, I_n, T_n, X, Y, Z, Tstar, gI_np1, gT_np1, gI_n, gT_n, gTstar, g_ka, g_j, st);
+    else reverse_step<double, RT_LIM_MINMOD>(c, a, I_n, T_n, X, Y, Z, Tstar, gI_np1, gT_np1, gI_n, gT_n, gTstar, g_ka, g_j, st);
+  }
   return hipGetLastError();
 }
 

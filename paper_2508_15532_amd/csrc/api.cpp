@@ -810,10 +810,41 @@ rt_status rt_step_adjoint(rt_ctx* c, const void* I_n, const double* T_n, double 
   if (st) return st;
   const size_t bytes = (size_t)c->ns * c->nc * c->elem;
   if ((st = alloc(&c->d_gA, bytes)) || (st = alloc(&c->d_gB, bytes)) || (st = alloc(&c->d_gC, bytes)) ||
-      (st = alloc(&c->d_gD, bytes)) || (st = alloc(&c->d_gcell, 6 * (size_t)c->nc * 8)))
+      (st = alloc(&c->d_gD, bytes)) || (st = alloc(&c->d_gcell, 6 * (size_t)c->nc * 8)) ||
+      (st = alloc(&c->d_gT, 2 * (size_t)c->nc * 8)))
     return st;
   RT_HIP(timed(c, RT_K_ADJOINT, stream, [&] {
-    return launch_adjoint_step(c, I_n, T_n, dt, gI_np1, gI_n, g_kappa_a, g_j, stream);
+    return launch_adjoint_step(c, I_n, T_n, dt, gI_np1, nullptr, gI_n, nullptr, g_kappa_a, g_j, stream);
+  }));
+  return RT_OK;
+}
+
+rt_status rt_step_adjoint_thermal(rt_ctx* c, const void* I_n, const double* T_n, double dt,
+                                  const void* gI_np1, const double* gT_np1, void* gI_n, double* gT_n,
+                                  double* g_kappa_a, hipStream_t stream) {
+  if (!c) return fail(RT_E_ARG, "rt_step_adjoint_thermal: ctx is NULL");
+  if (!c->metric_set || !c->opac_set)
+    return fail(RT_E_STATE, "rt_step_adjoint_thermal: set metric and opacities first");
+  if (c->opac.model != RT_OPAC_BREMS)
+    return fail(RT_E_ARG, "rt_step_adjoint_thermal: only the BREMS model (Method 2) is differentiated");
+  if (c->curved) return fail(RT_E_ARG, "rt_step_adjoint_thermal: only the flat metric is differentiated");
+  if (c->moving) return fail(RT_E_ARG, "rt_step_adjoint_thermal: fluid must be at rest");
+  if (!I_n || !T_n || !gI_np1 || !gI_n || !gT_n) return fail(RT_E_ARG, "rt_step_adjoint_thermal: NULL argument");
+  if (!aligned(I_n) || !aligned(T_n) || !aligned(gI_np1) || !aligned(gI_n) || !aligned(gT_n) ||
+      (gT_np1 && !aligned(gT_np1)) || (g_kappa_a && !aligned(g_kappa_a)))
+    return fail(RT_E_ARG, "rt_step_adjoint_thermal: arrays must be 256-byte aligned");
+  if (gT_n == T_n || (const void*)gT_n == (const void*)gT_np1)
+    return fail(RT_E_ARG, "rt_step_adjoint_thermal: gT_n may alias neither T_n nor gT_np1");
+  if (!(dt > 0.0) || dt > c->dt_max * (1.0 + 1e-12)) return fail(RT_E_ARG, "rt_step_adjoint_thermal: bad dt");
+  rt_status st = use_device(c);
+  if (st) return st;
+  const size_t bytes = (size_t)c->ns * c->nc * c->elem;
+  if ((st = alloc(&c->d_gA, bytes)) || (st = alloc(&c->d_gB, bytes)) || (st = alloc(&c->d_gC, bytes)) ||
+      (st = alloc(&c->d_gD, bytes)) || (st = alloc(&c->d_gcell, 6 * (size_t)c->nc * 8)) ||
+      (st = alloc(&c->d_gT, 2 * (size_t)c->nc * 8)))
+    return st;
+  RT_HIP(timed(c, RT_K_ADJOINT, stream, [&] {
+    return launch_adjoint_step(c, I_n, T_n, dt, gI_np1, gT_np1, gI_n, gT_n, g_kappa_a, nullptr, stream);
   }));
   return RT_OK;
 }
@@ -881,6 +912,7 @@ void rt_destroy(rt_ctx* c) {
   release(c->d_gC);
   release(c->d_gD);
   release(c->d_gcell);
+  release(c->d_gT);
   release(c->d_count);
   release(c->d_tile_order);
   release(c->d_rec_r);

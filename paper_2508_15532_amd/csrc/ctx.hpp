@@ -83,6 +83,7 @@ struct rt_ctx {
   void* d_gC = nullptr;
   void* d_gD = nullptr;
   double* d_gcell = nullptr;   // adjoint per-face tau gradients [3][2][nc]
+  double* d_gT = nullptr;      // adjoint: dL/dT* and a stage-2 temperature scratch [2][nc]
   unsigned long long* d_count = nullptr;  // [0] interaction failures, [1] non-finite
   // launch order of the stage kernel's tiles (bricks of tiles that run together),
   // cached per (tiles per axis, tile shape, resident workgroups)
@@ -150,8 +151,10 @@ hipError_t launch_moments(rt_ctx* c, const void* I, double* R, double* J, hipStr
 // R^(ab) (tetrad) -> R^(mu nu) = e^mu_a e^nu_b R^(ab) in place (curved geometry)
 hipError_t launch_to_coord(rt_ctx* c, double* R, hipStream_t st);
 hipError_t launch_nonfinite(rt_ctx* c, const void* I, const double* T, hipStream_t st);
+// one reverse step; gT_np1 (may be NULL) and gT_n are used by the
+// bremsstrahlung model only (gT_n is written, not accumulated)
 hipError_t launch_adjoint_step(rt_ctx* c, const void* I_n, const double* T_n, double dt,
-                               const void* gI_np1, void* gI_n, double* g_ka, double* g_j,
-                               hipStream_t st);
+                               const void* gI_np1, const double* gT_np1, void* gI_n, double* gT_n,
+                               double* g_ka, double* g_j, hipStream_t st);
 
 }  // namespace rt

@@ -94,7 +94,7 @@ __device__ __forceinline__ void opac(const StageArgs& a, const double* __restric
   double r = rho[c];
   if (a.model == RT_OPAC_BREMS || a.model == RT_OPAC_BREMS_M3) {
     const double t = T[c];
-    aa = a.C_a * r * r / (t * t * t * sqrt(t));  // T^-3.5
+    aa = a.C_a * r * r / (t * t * t * sqrt(t)) * (ka ? ka[c] : 1.0);  // T^-3.5, per-cell factor
     as = a.C_s * r;
   } else {
     aa = ka ? r * ka[c] : 0.0;
@@ -172,6 +172,8 @@ __device__ bool method3_root(double Y, double E0, double N, double as, double ab
   return false;
 }
 
+// jc: the emissivity (fixed-emissivity model) or the per-cell factor of the
+// bremsstrahlung opacity (1 when none is given)
 __device__ Solve solve_cell(const StageArgs& a, double r, double T0, double aa, double as,
                             double Em, double A1, double A2, double jc) {
   const double Y = r / (a.gamma - 1.0);
@@ -179,7 +181,7 @@ __device__ Solve solve_cell(const StageArgs& a, double r, double T0, double aa, 
   const double K = A1 - Y * q * T0 - q * Em;
   Solve o{T0, 0.0, 1.0, true};
   if (a.model == RT_OPAC_BREMS_M3) {
-    const double N = a.C_a * r * r, E0 = Em + Y * T0, ab = aa + as;
+    const double N = a.C_a * r * r * jc, E0 = Em + Y * T0, ab = aa + as;
     double Tp = T0;
     // with the Newton cap of Methods 1-2, at least the bisection depth of FP64
     if (!method3_root(Y, E0, N, as, ab, A1, A2, T0, max(a.max_iter, 120), a.rtol, Tp)) {
@@ -207,7 +209,7 @@ __device__ Solve solve_cell(const StageArgs& a, double r, double T0, double aa, 
   double Tp, Sp;
   if (a.model == RT_OPAC_BREMS) {
     // Method 2: A2 N sqrt(T) + Y q T + K = 0 is a quadratic in y = sqrt(T)
-    const double N = a.C_a * r * r;
+    const double N = a.C_a * r * r * jc;
     const double B = A2 * N;
     const double y = -2.0 * K / (B + sqrt(B * B - 4.0 * b * K));
     Tp = y * y;
@@ -767,7 +769,9 @@ k_stage(StageArgs a, StagePtrs p) {
     }
     Solve so{T0k, 0.0, 1.0, false};
     if (live) {
-      so = solve_cell(a, rrk, T0k, aak, ask, Em, A1, A2, p.jv ? p.jv[c] : 0.0);
+      const bool brems = a.model == RT_OPAC_BREMS || a.model == RT_OPAC_BREMS_M3;
+      const double jc = brems ? (p.ka ? p.ka[c] : 1.0) : (p.jv ? p.jv[c] : 0.0);
+      so = solve_cell(a, rrk, T0k, aak, ask, Em, A1, A2, jc);
       if (!so.ok && p.fail) atomicAdd(p.fail, 1ull);
     }
     const bool use = live && so.ok;

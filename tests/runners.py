@@ -166,3 +166,44 @@ def gpu_grad(wl, steps, I0, weights, precision="fp64", limiter="mc"):
     out = (g.double().cpu().reshape((ctx.ns,) + shape), gk.cpu().reshape(shape), gj.cpu().reshape(shape))
     ctx.close()
     return out
+
+
+def oracle_grad_thermal(wl, steps, I0, wI, wT, limiter=0):
+    """Reference gradient by torch autograd through the FP64 oracle for the
+    bremsstrahlung model: L = sum(wI * I_N) + sum(wT * T_N); returns
+    (dL/dI0, dL/dT0, dL/dkappa_a) with kappa_a the per-cell opacity factor."""
+    from oracle import step as st
+    from oracle.setup import build_flat
+    pb, _, T0 = build_flat(wl, limiter=limiter)
+    ka = (pb.kappa_a if pb.kappa_a is not None else pb.kappa_default()).clone().requires_grad_(True)
+    pb.kappa_a = ka
+    I = torch.as_tensor(I0, dtype=F64).reshape((pb.geo.grid.ns,) + tuple(wl["n"])).clone().requires_grad_(True)
+    T = T0.clone().requires_grad_(True)
+    X, Tx = I, T
+    for _ in range(steps):
+        X, Tx = st.step(pb, X, Tx, wl["dt"])
+    L = (torch.as_tensor(wI, dtype=F64).reshape(X.shape) * X).sum() + \
+        (torch.as_tensor(wT, dtype=F64).reshape(Tx.shape) * Tx).sum()
+    return torch.autograd.grad(L, [I, T, ka])
+
+
+def gpu_grad_thermal(wl, steps, I0, wI, wT, precision="fp64", limiter="mc"):
+    """(dL/dI0, dL/dT0, dL/dkappa_a) from the HIP adjoint of the bremsstrahlung
+    step, for L = sum(wI * I_N) + sum(wT * T_N)."""
+    ctx = gpu_context(wl, precision, limiter)
+    I, T = gpu_initial(ctx, wl, I0)
+    states = []
+    for _ in range(steps):
+        states.append((I.clone(), T.clone()))
+        ctx.step(I, T, wl["dt"], 1)
+    gI = torch.as_tensor(np.ascontiguousarray(wI), dtype=F64).reshape(ctx.ns, -1).to(ctx.intensity_dtype)
+    gI = gI.cuda().contiguous()
+    gT = torch.as_tensor(np.ascontiguousarray(wT), dtype=F64).reshape(-1).cuda().contiguous()
+    gk = torch.zeros(ctx.nc, dtype=F64, device="cuda")
+    for I_k, T_k in reversed(states):
+        gI, gT = ctx.step_adjoint_thermal(I_k, T_k, wl["dt"], gI, gT, gI_n=gI, g_kappa_a=gk)
+    torch.cuda.synchronize()
+    shape = tuple(wl["n"])
+    out = (gI.double().cpu().reshape((ctx.ns,) + shape), gT.cpu().reshape(shape), gk.cpu().reshape(shape))
+    ctx.close()
+    return out

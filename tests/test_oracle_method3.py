@@ -42,7 +42,7 @@ def _interact_diag(rho, T0, I0, h, C_s, model="brems_m3", aniso=0.0, seed=0):
     d = {}
     Iout, Tout, failed = src.interact(
         I, T, T, pb.rho, pb.u_hat, torch.ones((1, 1, 1), dtype=F64), torch.tensor(g.n, dtype=F64),
-        torch.tensor(g.w, dtype=F64), h, pb.model, pb.gamma, pb.zeros(), pb.zeros(), pb.zeros(),
+        torch.tensor(g.w, dtype=F64), h, pb.model, pb.gamma, pb.kappa_default(), pb.zeros(), pb.zeros(),
         pb.C_a, pb.C_s, pb.rho_floor, diag=d)
     return I, Iout, Tout, failed, d, g
 
