@@ -19,35 +19,61 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X published HBM3E bandwidth
 MFMA_F64_PEAK_TFS = 78.6       # MI355X published dense FP64 matrix-core rate
+# VALU issue: 256 compute units x 4 SIMDs at 2.4 GHz; a 64-lane VALU
+# instruction occupies a 16-lane SIMD for 4 cycles (no packed FP32 here), i.e.
+# 39.3e12 lane-instructions/s (the 157.3 TFLOP/s FP32 figure counts FMA as two
+# flops and packed pairs as two lanes)
+SIMDS, CLOCK_HZ, VALU_CYCLES = 256 * 4, 2.4e9, 4
+VALU_PEAK_TLANE = SIMDS * 16 * CLOCK_HZ / 1e12
 CSRC = os.path.join(ROOT, "paper_2508_15532_amd", "csrc")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+ACCURACY_FILE = os.path.join(ROOT, "profiles", "accuracy_fp32_vs_oracle.json")
+
+
+# Per-cell bytes the method moves besides the intensities (per stage): the
+# fluid fields rho, kappa_a, kappa_s or j and u^mu (7 x 8 B), and the
+# temperatures: stage 1 reads T^n and writes T*, stage 2 reads T^n and T* and
+# writes T^(n+1).  R^(ab) (10 x 8 B) where it is formed.
+FIELDS_B = 56
+R_B = 80
 
 
 def algorithmic_bytes(kind, elem, ns, nc):
-    """Bytes a launch of each kernel must move at minimum (its inputs read once
-    and its outputs written once), per launch over the whole grid."""
+    """Bytes a launch of each kernel must move at minimum, counted as the
+    method's own transfers: intensities (stage 1 reads I^n and writes I*,
+    stage 2 reads I* and I^n and writes I^(n+1)), the per-cell temperatures and
+    fluid fields, and R where it is formed.  The lazy interaction maps, halo
+    re-reads and the angular-divergence scratch are implementation overhead and
+    are not counted (they show in the measured traffic instead)."""
     cd = ns * nc
-    if kind == "stage1":       # read I^n, write I~; per cell: map, T, rho in; T*, map out
-        return 2 * elem * cd + 56 * nc
-    if kind == "stage2":       # read I*, I^n, write I~; per cell: 2 maps, T, T*, rho in; T, map, R out
-        return 3 * elem * cd + 160 * nc
-    if kind == "materialize":  # read I~, write I; per cell: map
-        return 2 * elem * cd + 16 * nc
+    if kind == "stage1":
+        return 2 * elem * cd + (16 + FIELDS_B) * nc
+    if kind == "stage2":
+        return 3 * elem * cd + (24 + FIELDS_B) * nc
+    if kind == "materialize":  # read I~, write I^(n+1), R^(ab) out
+        return 2 * elem * cd + R_B * nc
     if kind == "moments":      # read I, write 10 components
-        return elem * cd + 80 * nc
+        return elem * cd + R_B * nc
+    if kind == "angular":      # read I, write the angular divergence
+        return 2 * elem * cd
+    if kind == "adjoint":      # one reverse step: the forward step it re-runs plus its mirror
+        return 2 * (5 * elem * cd + (40 + 2 * FIELDS_B) * nc)
     raise KeyError(kind)
 
 
 def step_algorithmic_bytes(elem, ns, nc):
-    """Per step, what the method itself must move: stage 1 reads I^n and writes
-    I*, stage 2 reads I* and I^n and writes I^(n+1) (5 intensity transfers per
-    cell-direction), plus R (80 B per cell)."""
-    return 5 * elem * ns * nc + 80 * nc
+    """Per step, what the method itself must move: 5 intensity transfers per
+    cell-direction (stage 1: I^n in, I* out; stage 2: I*, I^n in, I^(n+1) out),
+    per cell the temperatures (5 x 8 B) and the fluid fields of both stages
+    (2 x 56 B), and R^(ab) of the new intensity (80 B)."""
+    return 5 * elem * ns * nc + (40 + 2 * FIELDS_B + R_B) * nc
 
 
 def make_inputs(wl, ctx, torch):
@@ -56,7 +82,9 @@ def make_inputs(wl, ctx, torch):
     def t(x):
         return None if x is None else torch.as_tensor(x, dtype=torch.float64).reshape(-1).to(dev)
     rho, T, u = t(wl["rho"]), t(wl["T"]), t(wl.get("u"))
-    ctx.set_opacities(wl["model"], rho, u=u, gamma=wl["gamma"], C_a=wl["C_a"], C_s=wl["C_s"])
+    ka, ks, j = t(wl.get("kappa_a")), t(wl.get("kappa_s")), t(wl.get("j"))
+    ctx.set_opacities(wl["model"], rho, u=u, kappa_a=ka, kappa_s=ks, j=j, gamma=wl["gamma"], C_a=wl["C_a"],
+                      C_s=wl["C_s"])
     if wl.get("metric") == "kerr_schild":
         I0 = torch.as_tensor(wl["I0_iso"], dtype=torch.float64).reshape(-1).to(dev)
     else:
@@ -64,7 +92,7 @@ def make_inputs(wl, ctx, torch):
     I = I0.reshape(1, -1).expand(ctx.ns, -1).to(ctx.intensity_dtype).contiguous()
     R = torch.empty((10, ctx.nc), dtype=torch.float64, device=dev)
     G = torch.empty((4, ctx.nc), dtype=torch.float64, device=dev)
-    return (rho, u, G), I, T, R
+    return (rho, u, G, ka, ks, j), I, T, R
 
 
 def make_context(wl, precision, P):
@@ -122,17 +150,49 @@ def sources_sha256():
     return h.hexdigest()
 
 
-def traffic_for(kernel, elem):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
-    summary, if it was taken on the current sources; else None."""
+def counters_for(wkey, kernel, elem):
+    """Per-launch HBM bytes (rocprofv3 FETCH_SIZE + WRITE_SIZE, scaled by the
+    plain-copy calibration) and VALU wave-instructions (SQ_INSTS_VALU) of
+    `kernel` on workload `wkey`, from the committed counter record, if it was
+    taken on the current library sources; else None."""
     try:
         with open(TRAFFIC_FILE) as f:
             rec = json.load(f)
         if rec.get("sources_sha256") != sources_sha256():
             return None
-        return rec["per_launch_bytes"].get(f"{kernel}_{'fp32' if elem == 4 else 'fp64'}")
+        return rec["per_launch"].get(f"{wkey}/{kernel}_{'fp32' if elem == 4 else 'fp64'}")
     except (OSError, KeyError, ValueError):
         return None
+
+
+def roofline_block(wkey, r):
+    """Roofline of the dominant kernel of a timed run: its algorithmic bytes over
+    its mean HIP-event duration against the HBM peak, and, where the committed
+    counters of the current sources exist, its measured HBM traffic and VALU
+    issue.  The bound is the busier of the two units: HBM (measured traffic, or
+    the algorithmic bytes without counters, over the peak) or VALU issue
+    (wave-instructions x 4 cycles over the SIMD-cycles of the launch)."""
+    kt = {k: v for k, v in r["ktimes"].items() if v[0] > 0}
+    dom = max(kt, key=lambda k: kt[k][1])
+    launches, tot_ms = kt[dom]
+    t = tot_ms / launches / 1e3
+    abytes = algorithmic_bytes(dom, r["elem"], r["ns"], r["nc"])
+    hbm = abytes / t / 1e9
+    cnt = counters_for(wkey, dom, r["elem"]) or {}
+    traffic, valu = cnt.get("bytes"), cnt.get("valu_insts")
+    hbm_busy = (traffic if traffic else abytes) / t / 1e9 / HBM_PEAK_GBS
+    blk = {"bound": "hbm", "achieved": hbm, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": hbm / HBM_PEAK_GBS,
+           "traffic": traffic, "kernel": dom, "kernel_avg_ms": t * 1e3,
+           "algorithmic_bytes": abytes, "hbm_frac_algorithmic": hbm / HBM_PEAK_GBS,
+           "hbm_busy_measured": (traffic / t / 1e9 / HBM_PEAK_GBS) if traffic else None}
+    if valu:
+        valu_busy = valu * VALU_CYCLES / (SIMDS * CLOCK_HZ * t)
+        blk["valu_busy"] = valu_busy
+        if valu_busy > hbm_busy:
+            # VALU issue bound: achieved = lane-instructions issued per second
+            blk.update(bound="alu", achieved=valu * 64 / t / 1e12, peak=VALU_PEAK_TLANE,
+                       unit="T VALU lane-instructions/s", frac=valu_busy)
+    return blk
 
 
 def cpu_baseline(torch):
@@ -185,6 +245,137 @@ def run_moments(wl, precision, launches, warmup, torch, P):
             "mfma_f64_TFLOPs": tflops, "mfma_frac": tflops / MFMA_F64_PEAK_TFS}
 
 
+def step_frac(r, steps):
+    """Fraction of the HBM peak that the method's own bytes per step
+    (step_algorithmic_bytes) over the measured wall time per step amount to."""
+    return step_algorithmic_bytes(r["elem"], r["ns"], r["nc"]) * steps / r["wall"] / 1e9 / HBM_PEAK_GBS
+
+
+def line_entry(desc, wkey, r, steps):
+    return {"workload": desc,
+            "value": r["ns"] * r["nc"] * steps / r["wall"],
+            "unit": "cell-direction updates/s",
+            "steps": steps,
+            "ms_per_step": 1e3 * r["wall"] / steps,
+            "roofline": roofline_block(wkey, r),
+            "step_hbm_frac": step_frac(r, steps),
+            "kernels_ms_per_step": {k: v[1] / steps for k, v in r["ktimes"].items() if v[0]},
+            "finite": r["finite"]}
+
+
+def run_adjoint(torch, P):
+    """The adjoint workload: flat 64^3 x 162, FP32, fixed emissivity
+    (lognormal kappa_a, j ~ U[0, 1]), zero-incoming faces, 20 steps with the
+    loss gradient flowing back through the checkpointed autograd Function
+    (checkpoints every 5 steps: forward 20 steps, backward re-runs 15 steps and
+    applies 20 adjoint steps).  Reports the time of a whole forward + backward
+    and the mean duration of one rt_step_adjoint (HIP events)."""
+    import workloads as W
+    from paper_2508_15532_amd.autograd import RTSteps
+    wl = W.adjoint_flat()
+    ctx = P.RTContext(wl["n"], wl["xlo"], wl["xhi"], wl["generation"], weights=wl["weights"],
+                      precision="fp32", bc=wl["bc"])
+    ctx.set_metric("flat", cfl=0.4)
+    dev = torch.device("cuda", 0)
+    f64 = torch.float64
+    rho = torch.as_tensor(wl["rho"], dtype=f64).reshape(-1).to(dev)
+    opac = dict(rho=rho, kappa_s=torch.zeros_like(rho))
+    ka = torch.as_tensor(wl["kappa_a"], dtype=f64).reshape(-1).to(dev)
+    jj = torch.as_tensor(wl["j"], dtype=f64).reshape(-1).to(dev)
+    I0 = torch.zeros((ctx.ns, ctx.nc), dtype=torch.float32, device=dev)
+    T = torch.as_tensor(wl["T"], dtype=f64).reshape(-1).to(dev)
+    dirs, w, _ = ctx.grid()
+    wts = torch.zeros((ctx.ns,) + tuple(wl["n"]), dtype=torch.float32)
+    wts[:, -1] = torch.as_tensor(w * np.maximum(dirs[:, 0], 0.0), dtype=torch.float32)[:, None, None]
+    wts = wts.reshape(ctx.ns, -1).to(dev)
+
+    def once():
+        k = ka.clone().requires_grad_(True)
+        j = jj.clone().requires_grad_(True)
+        IN = RTSteps.apply(ctx, I0, k, j, T, wl["dt"], wl["steps"], wl["checkpoint"], opac)
+        (IN * wts).sum().backward()
+        return k.grad
+
+    once()
+    torch.cuda.synchronize()
+    ctx.set_debug(2)
+    ctx.kernel_times()
+    t0 = time.perf_counter()
+    g = once()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kt = ctx.kernel_times()
+    ctx.set_debug(0)
+    n_adj, ms_adj = kt["adjoint"]
+    ns, nc = ctx.ns, ctx.nc
+    ctx.close()
+    t = ms_adj / n_adj / 1e3
+    ab = algorithmic_bytes("adjoint", 4, ns, nc)
+    return {"workload": "flat 64^3 x 162, FP32, fixed emissivity, 20 steps, checkpoints every 5, "
+                        "gradient of the +x outgoing flux w.r.t. kappa_a and j",
+            "forward_backward_ms": wall * 1e3,
+            "adjoint_steps": n_adj,
+            "adjoint_ms_per_step": t * 1e3,
+            "adjoint_cell_direction_steps_per_s": ns * nc / t,
+            "roofline": {"bound": "hbm", "achieved": ab / t / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": ab / t / 1e9 / HBM_PEAK_GBS, "traffic": None, "kernel": "adjoint step",
+                         "algorithmic_bytes": ab},
+            "finite": bool(torch.isfinite(g).all().item())}
+
+
+def run_only(which, steps, warmup, torch, P, W):
+    """One of the secondary lines: the Kerr-Schild torus with donor-cell or
+    MAPR angular states, the turbulent torus with 642 directions, or the
+    adjoint workload."""
+    if which == "torus":
+        # curved geometry: the a = 0.9 Kerr-Schild torus, FP32 transport form
+        print(f"bench: torus_ks fp32 256x128x64 x 162, {steps} steps", file=sys.stderr, flush=True)
+        tr = run_form(W.torus_ks(), "fp32", steps, warmup, torch, P, per_call=True)
+        return line_entry("Kerr-Schild a=0.9 torus, (ln r, theta, phi) 256x128x64 x 162 directions, "
+                          "Keplerian flow, Method 2, FP32 transport, donor-cell angular states",
+                          "torus256", tr, steps)
+    if which == "mapr":
+        # the same torus with MAPR angular edge states (two kernels in place of
+        # the donor-cell angular kernel)
+        print(f"bench: torus_ks mapr fp32 256x128x64 x 162, {steps} steps", file=sys.stderr, flush=True)
+        mr = run_form(dict(W.torus_ks(), angular_recon="mapr"), "fp32", steps, warmup, torch, P, per_call=True)
+        return line_entry("Kerr-Schild a=0.9 torus, 256x128x64 x 162 directions, MAPR angular states, "
+                          "FP32 transport", "torus256mapr", mr, steps)
+    if which == "bigtorus":
+        # the largest configuration: 6.1e9 cell-directions, 24 GB per FP32 intensity copy
+        print(f"bench: turbulent torus fp32 384x192x128 x 642, {warmup} warmup + {steps} timed steps",
+              file=sys.stderr, flush=True)
+        bw = W.torus_ks(n=(384, 192, 128), generation=3, sigma_ln=0.7, scattering=True)
+        br = run_form(bw, "fp32", steps, warmup, torch, P, per_call=True)
+        return line_entry("Kerr-Schild a=0.9 turbulent torus (lognormal sigma_ln 0.7, scattering), "
+                          "(ln r, theta, phi) 384x192x128 x 642 directions, FP32 transport",
+                          "torus384g3", br, steps)
+    if which == "adjoint":
+        print("bench: adjoint 64^3 x 162 fp32, 20 steps, checkpoints every 5", file=sys.stderr, flush=True)
+        return run_adjoint(torch, P)
+    if which == "sphere":
+        # the curved-coordinate validation workload at the torus line's size
+        print(f"bench: bright sphere fp32 256x128x64 x 162, {steps} steps", file=sys.stderr, flush=True)
+        sw = W.bright_sphere(n=(256, 128, 64), generation=2)
+        sr = run_form(sw, "fp32", steps, warmup, torch, P, per_call=True)
+        return line_entry("emitting ball in flat space, (ln r, theta, phi) 256x128x64 x 162 directions, "
+                          "fixed emissivity, FP32 transport", "sphere256", sr, steps)
+    raise KeyError(which)
+
+
+def accuracy_record():
+    """Per-field error of the FP32 form against the FP64 oracle, as measured by
+    tests/test_gpu_accuracy.py (RT_ACCURACY_OUT) and committed with its
+    sources' hash; None when absent or taken on other sources."""
+    try:
+        with open(ACCURACY_FILE) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    rec["current_sources"] = rec.get("sources_sha256") == sources_sha256()
+    return rec
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -199,7 +390,13 @@ def main():
     ap.add_argument("--no-mapr", action="store_true",
                     help="skip the torus line with MAPR angular states (256x128x64 x 162, FP32)")
     ap.add_argument("--no-big-torus", action="store_true",
-                    help="skip the large turbulent-torus line (384x192x128 x 642, FP32, 3 steps)")
+                    help="skip the large turbulent-torus line (384x192x128 x 642, FP32, 5 steps)")
+    ap.add_argument("--no-sphere", action="store_true",
+                    help="skip the curved-coordinate validation line (bright sphere 256x128x64 x 162, FP32)")
+    ap.add_argument("--no-adjoint", action="store_true",
+                    help="skip the adjoint line (64^3 x 162 FP32, 20 steps, checkpoints every 5)")
+    ap.add_argument("--only", choices=["torus", "mapr", "bigtorus", "adjoint", "sphere"],
+                    help="run only that line (for profiling) and print it as one JSON object")
     ap.add_argument("--moments-only", action="store_true",
                     help="only time rt_moments on the 128^3 x 162 field (FP32 and FP64) and print it")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -231,6 +428,9 @@ def main():
     if args.moments_only:
         print(json.dumps({"moments": [run_moments(wl, prec, 10, 2, torch, P) for prec in forms]}))
         return
+    if args.only:
+        print(json.dumps(run_only(args.only, args.steps, args.warmup, torch, P, W)))
+        return
     res = {}
     for prec in forms:
         print(f"bench: {prec} 128^3 x 162, {args.warmup} warmup + {args.steps} timed steps",
@@ -245,15 +445,6 @@ def main():
     cd_per_step = r["ns"] * r["nc"]
     value = cd_per_step * args.steps / r["wall"]
     ms_per_step = 1e3 * r["wall"] / args.steps
-    # roofline of the dominant kernel, from HIP events over the timed region
-    kt = {k: v for k, v in r["ktimes"].items() if v[0] > 0}
-    dom = max(kt, key=lambda k: kt[k][1])
-    launches, tot_ms = kt[dom]
-    avg_s = tot_ms / launches / 1e3
-    abytes = algorithmic_bytes(dom, r["elem"], r["ns"], r["nc"])
-    achieved = abytes / avg_s / 1e9
-    traffic = traffic_for(dom, r["elem"])
-    step_bytes = step_algorithmic_bytes(r["elem"], r["ns"], r["nc"])
     out = {
         "metric": "cell-direction updates/s for rt_step (FP32 vs FP64) + % HBM roofline",
         "value": value,
@@ -274,15 +465,15 @@ def main():
                    "step": "one rt_step call per step: predictor-corrector step incl. R^(ab) "
                            "and the 4-force of the new intensity",
                    "parallelism": "single GPU"},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": dom,
-                     "kernel_avg_ms": avg_s * 1e3,
-                     "step_frac": step_bytes * args.steps / r["wall"] / 1e9 / HBM_PEAK_GBS},
+        "roofline": roofline_block("flat128", r),
+        "step_hbm_frac": step_frac(r, args.steps),
         "kernels_ms_per_step": {k: v[1] / args.steps for k, v in r["ktimes"].items() if v[0]},
     }
     for prec, rr in res.items():
         out[f"value_{prec}"] = rr["ns"] * rr["nc"] * args.steps / rr["wall"]
         out[f"ms_per_step_{prec}"] = 1e3 * rr["wall"] / args.steps
+        out[f"roofline_{prec}"] = roofline_block("flat128", rr)
+        out[f"step_hbm_frac_{prec}"] = step_frac(rr, args.steps)
         if not rr["finite"]:
             out["error"] = f"non-finite moments in the {prec} run"
     if multi is not None:
@@ -292,64 +483,25 @@ def main():
     if "fp32" in res and "fp64" in res:
         out["speedup_fp32_over_fp64"] = out["value_fp32"] / out["value_fp64"]
     if not args.no_torus:
-        # curved geometry: the a = 0.9 Kerr-Schild torus, FP32 transport form
-        print("bench: torus_ks fp32 256x128x64 x 162", file=sys.stderr, flush=True)
-        tw = W.torus_ks()
-        tr = run_form(tw, "fp32", args.steps, args.warmup, torch, P, per_call=True)
-        out["torus_ks"] = {
-            "workload": "Kerr-Schild a=0.9 torus, (ln r, theta, phi) 256x128x64 x 162 directions, "
-                        "Keplerian flow, Method 2, FP32 transport",
-            "value": tr["ns"] * tr["nc"] * args.steps / tr["wall"],
-            "unit": "cell-direction updates/s",
-            "ms_per_step": 1e3 * tr["wall"] / args.steps,
-            "kernels_ms_per_step": {k: v[1] / args.steps for k, v in tr["ktimes"].items() if v[0]},
-            "finite": tr["finite"]}
+        out["torus_ks"] = run_only("torus", args.steps, args.warmup, torch, P, W)
     if not args.no_mapr:
-        # the same torus with MAPR angular edge states (two kernels in place of the
-        # donor-cell angular kernel); algorithmic HBM bytes of the pair per
-        # cell-direction: slope pass reads I, writes the 2-component slope; flux
-        # pass reads I and both slope components, writes D (neighbour rows are
-        # cache reuse, the per-(r, theta) coefficient rows are shared along phi)
-        msteps = min(args.steps, 5)
-        print(f"bench: torus_ks mapr fp32 256x128x64 x 162, {msteps} steps", file=sys.stderr, flush=True)
-        mw = dict(W.torus_ks(), angular_recon="mapr")
-        mr = run_form(mw, "fp32", msteps, 1, torch, P, per_call=True)
-        kms = {k: v[1] / msteps for k, v in mr["ktimes"].items() if v[0]}
-        entry = {
-            "workload": "Kerr-Schild a=0.9 torus, 256x128x64 x 162 directions, MAPR angular states, "
-                        "FP32 transport",
-            "value": mr["ns"] * mr["nc"] * msteps / mr["wall"],
-            "unit": "cell-direction updates/s",
-            "ms_per_step": 1e3 * mr["wall"] / msteps,
-            "kernels_ms_per_step": kms,
-            "finite": mr["finite"]}
-        n_ang, ms_ang = mr["ktimes"].get("angular", (0, 0.0))
-        if n_ang:
-            per_launch_ms = ms_ang / n_ang          # one evaluation per stage
-            entry["angular_mapr_ms_per_launch"] = per_launch_ms
-            entry["angular_mapr_hbm_GBps"] = 7 * mr["elem"] * mr["ns"] * mr["nc"] / (per_launch_ms * 1e-3) / 1e9
-        out["torus_ks_mapr"] = entry
+        out["torus_ks_mapr"] = run_only("mapr", min(args.steps, 5), 1, torch, P, W)
     if not args.no_big_torus:
-        # the largest configuration: 6.1e9 cell-directions, 24 GB per FP32 intensity copy
-        print("bench: turbulent torus fp32 384x192x128 x 642, 1 warmup + 3 timed steps",
-              file=sys.stderr, flush=True)
         try:
-            bw = W.torus_ks(n=(384, 192, 128), generation=3, sigma_ln=0.7, scattering=True)
-            br = run_form(bw, "fp32", 3, 1, torch, P, per_call=True)
-            out["torus_ks_384x192x128_g3"] = {
-                "workload": "Kerr-Schild a=0.9 turbulent torus (lognormal sigma_ln 0.7, scattering), "
-                            "(ln r, theta, phi) 384x192x128 x 642 directions, FP32 transport",
-                "value": br["ns"] * br["nc"] * 3 / br["wall"],
-                "unit": "cell-direction updates/s",
-                "ms_per_step": 1e3 * br["wall"] / 3,
-                "kernels_ms_per_step": {k: v[1] / 3 for k, v in br["ktimes"].items() if v[0]},
-                "finite": br["finite"]}
+            out["torus_ks_384x192x128_g3"] = run_only("bigtorus", 5, 1, torch, P, W)
         except Exception as e:  # reported in the line, the headline stands
             out["torus_ks_384x192x128_g3"] = {"error": f"{type(e).__name__}: {e}"}
+    if not args.no_adjoint:
+        out["adjoint"] = run_only("adjoint", 0, 0, torch, P, W)
+    if not args.no_sphere:
+        out["bright_sphere"] = run_only("sphere", min(args.steps, 10), 2, torch, P, W)
     # the standalone moment contraction (inside rt_step R is formed in the
     # materialisation pass instead)
     print("bench: rt_moments 128^3 x 162", file=sys.stderr, flush=True)
     out["moments"] = [run_moments(wl, prec, 10, 2, torch, P) for prec in forms]
+    acc = accuracy_record()
+    if acc is not None:
+        out["accuracy_fp32_vs_oracle"] = acc
     if not args.no_cpu_baseline:
         print("bench: CPU oracle baseline", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(torch)
