@@ -63,3 +63,14 @@ def build_ks(wl, grid=None, limiter=tr.LIM_MC, fd_h=1e-3):
                  angular=geo.angular, pole_rows=wl.get("pole_rows", 0))
     I0 = _t(wl["I0_iso"]).unsqueeze(0).expand((grid.ns,) + shape).clone()
     return pb, I0, _t(wl["T"]).clone(), geo.dt_max(wl.get("cfl", 0.4))
+
+
+def build_flat_mg(wl, grid=None, limiter=tr.LIM_MC):
+    """Multi-group inputs: (Problem, kappa_a per bin [G, *n], bin edges,
+    I0 [G, Ns, *n] (isotropic per bin), T0)."""
+    pb, _, T0 = build_flat(wl, grid, limiter)
+    ka = _t(wl["kappa_a_groups"])
+    ns = pb.geo.grid.ns
+    shape = tuple(wl["n"])
+    I0 = _t(wl["I0_iso_groups"]).unsqueeze(1).expand((ka.shape[0], ns) + shape).clone()
+    return pb, ka, tuple(wl["group_edges"]), I0, T0

@@ -17,6 +17,9 @@ Workloads (sizes of the paper-scale runs; every builder accepts a reduced
   adjoint_flat   flat 64^3, zero-incoming on all faces, generation 2,
                  kappa_a lognormal (sigma_ln = 0.5), j ~ U[0,1], rho = 1,
                  fixed emissivity, I0 = 0, dt 0.4, 20 steps.
+  multigroup_flat  the flat recipe with 4 frequency bins, per-bin absorption
+                 opacities rho^2 (3, 1, 0.3, 0.1), alpha^s = rho, bins
+                 starting with equal shares of T^4/(4 pi).
   torus_ks       Kerr-Schild a = 0.9, log r in [ln 1.5, ln 50], theta in
                  [0, pi], phi in [0, 2 pi); synthetic torus density, Keplerian
                  4-velocity outside the ISCO, T0 = 1, Method 2.
@@ -98,6 +101,33 @@ def adjoint_flat(n=64, generation=2, seed=None, n_probe=32):
         model="fixed_emissivity", gamma=5.0 / 3.0,
         rho=np.ones(shape), T=np.ones(shape), kappa_a=kappa, kappa_s=np.zeros(shape), j=j,
         u=None, I0_iso=np.zeros(shape), dt=0.4, steps=20, checkpoint=5, probes=probes,
+    )
+
+
+def multigroup_flat(n=128, generation=2, seed=None,
+                    edges=(0.0, 1.0, 3.0, 9.0, math.inf), kappa_groups=(3.0, 1.0, 0.3, 0.1)):
+    """Multi-group version of the flat recipe: rho lognormal (sigma_ln 1), T ~
+    U[0.5, 2], bins [0, 1), [1, 3), [3, 9), [9, inf) of fluid-frame frequency
+    (units of k_B/h), absorption opacity per bin kappa_a,g = rho kappa_g with
+    kappa_g = 3, 1, 0.3, 0.1 (alpha^a_g = rho^2 kappa_g, falling with
+    frequency), alpha^s = rho, periodic, dt 0.4; every bin starts isotropic
+    with an equal share T^4/(4 pi G) of the gray energy (out of equilibrium
+    across bins)."""
+    rng = rng_for(5, seed)
+    shape = (n, n, n) if np.isscalar(n) else tuple(n)
+    rho = lognormal(shape, 1.0, rng)
+    T = rng.uniform(0.5, 2.0, size=shape)
+    G = len(kappa_groups)
+    assert len(edges) == G + 1
+    return dict(
+        name="multigroup_flat", n=shape, xlo=(0.0, 0.0, 0.0), xhi=tuple(float(m) for m in shape),
+        generation=generation, weights="voronoi", bc=("periodic",) * 3,
+        model="kirchhoff_const", gamma=5.0 / 3.0,
+        rho=rho, T=T, kappa_a=None, kappa_s=np.ones(shape), j=None, u=None,
+        group_edges=tuple(float(e) for e in edges),
+        kappa_a_groups=np.stack([rho * k for k in kappa_groups]),
+        I0_iso_groups=np.stack([T ** 4 / (4.0 * math.pi * G)] * G),
+        I0_iso=T ** 4 / (4.0 * math.pi), dt=0.4, steps=20,
     )
 
 
