@@ -169,12 +169,42 @@ rt_status rt_set_metric(rt_ctx* ctx, int kind, double M, double a, double cfl, d
    freed once the stream has passed this call. */
 rt_status rt_set_opacities(rt_ctx* ctx, const rt_opacity_desc* desc, hipStream_t stream);
 
+/* Multi-group transport: split the radiation into ng bins of fluid-frame
+   frequency (Sec. 3.1, Eq. radiative_transfer_discrete_non_gray).  Read here
+   for a fluid at rest in flat space, where the photon frequency does not change
+   along a path, so the frequency flux r^nu vanishes and each bin is
+   transported as the gray equation with its own optical depth; the bins couple
+   through the gas temperature.  Per bin: absorption alpha^a_g = rho
+   kappa_a,g, emission by Kirchhoff's law with the bin-integrated Planck
+   function B_g(T) = int B_nu(T) dnu (units a_rad = k_B = h = 1, so the bins
+   of [0, inf) sum to T^4/(4 pi)), elastic isotropic scattering alpha^s = rho
+   kappa_s (kappa_s of rt_set_opacities) inside the bin.  The interaction is
+   Method 1's semi-implicit update in every bin with the temperature equation
+   Y (T_+ - T_-) = -sum_g (E+_g - E-_g), solved per cell by safeguarded
+   Newton (failures counted as for rt_step).
+     ng              number of bins, 1..RT_MAX_GROUPS; 0 switches back to gray.
+     nu_edges_host   host [ng + 1]: 0 <= nu_0 < nu_1 < ... < nu_ng; nu_ng may
+                     be +INFINITY.  Copied.
+     kappa_a_groups  device [ng][Nc] FP64, 256-byte aligned: kappa_a,g per
+                     cell.  Copied on `stream` (the source may be freed once
+                     the stream has passed this call).
+   Needs rt_set_metric (RT_FLAT) and rt_set_opacities (RT_OPAC_KIRCHHOFF_CONST,
+   fluid at rest) first, else RT_E_STATE; bad sizes or edges give RT_E_ARG.
+   While bins are set, rt_step and rt_step_noalloc take I as [ng][Ns][Nc] (bin
+   major) and return R_out and G_out summed over the bins; a later
+   rt_set_opacities that leaves this configuration makes rt_step return
+   RT_E_STATE.  The adjoints do not support bins (RT_E_ARG). */
+#define RT_MAX_GROUPS 64
+rt_status rt_set_groups(rt_ctx* ctx, int ng, const double* nu_edges_host, const double* kappa_a_groups,
+                        hipStream_t stream);
+
 /* Advance nsteps predictor-corrector steps (Sec. 3.7):
      stage 1: I~ = I^n - dt/2 div F(I^n); (I*, T*) = interaction(I~, dt/2, T^n, T^n)
      stage 2: I~ = I^n - dt   div F(I*);  (I^n+1, T^n+1) = interaction(I~, dt, T^n, T*)
    where interaction(I~, h, T_start, T_coef) uses explicit opacities at T_coef
    and starts the energy balance from T_start.
-   I     in/out [Ns][Nc] (element type per precision), T in/out [Nc].
+   I     in/out [Ns][Nc] (element type per precision; [ng][Ns][Nc] while
+         frequency bins are set, see rt_set_groups), T in/out [Nc].
    G_out optional [4][Nc]: tetrad-frame 4-force on the fluid of the last
          step's second interaction, -(R^(0a)(after) - R^(0a)(before))/dt.
    R_out optional [10][Nc]: moments (as rt_moments, tetrad frame, FP64 sums of
@@ -201,7 +231,8 @@ rt_status rt_step(rt_ctx* ctx, void* I, double* T, double dt, int nsteps, double
    contexts) race and must be serialised by the caller.  Errors: RT_E_ARG as
    rt_step, and when the grid needs more than 64 MiB of step scratch
    (about Nc * (Ns * elem + 56) bytes flat, plus Ns * Nc * elem curved and
-   2 Ns * Nc * elem more with MAPR); RT_E_STATE when the array's device address
+   2 Ns * Nc * elem more with MAPR; with ng frequency bins about
+   Nc * (ng (Ns * elem + 40) + 8)); RT_E_STATE when the array's device address
    could not be resolved at rt_init_grid. */
 rt_status rt_step_noalloc(rt_ctx* ctx, void* I, double* T, double dt, int nsteps, double* G_out,
                           double* R_out, hipStream_t stream);
@@ -250,7 +281,9 @@ rt_status rt_set_debug(rt_ctx* ctx, int flags);
    (counts[k]) and their summed duration in milliseconds (ms[k]) since the
    previous call, then starts a new tally.  Either output may be NULL. */
 enum { RT_K_STAGE1 = 0, RT_K_STAGE2, RT_K_MATERIALIZE, RT_K_MOMENTS, RT_K_ADJOINT,
-       RT_K_ANGULAR /* curved: angular flux divergence before each stage */, RT_NKERNELS };
+       RT_K_ANGULAR /* curved: angular flux divergence before each stage */,
+       RT_K_MG_SOLVE /* frequency bins: temperature solve and per-bin maps of each stage */,
+       RT_NKERNELS };
 rt_status rt_kernel_times(rt_ctx* ctx, int* counts, double* ms);
 
 /* Number of cells whose interaction found no valid temperature root (they

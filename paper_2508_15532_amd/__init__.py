@@ -92,6 +92,7 @@ class RTContext:
         self.ns = ns.value
         self._keep = []
         self.dt_max = None
+        self.ng = 0
 
     # -- grid ---------------------------------------------------------------
     def grid(self):
@@ -133,13 +134,30 @@ class RTContext:
         # the copies are asynchronous: keep the sources alive until the stream passes
         self._keep = [rho, u, kappa_a, kappa_s, j]
 
+    def set_groups(self, edges, kappa_a_groups):
+        """Frequency bins (fluid at rest, flat space): edges, G + 1 increasing
+        values (the last may be inf), kappa_a_groups [G, *n] float64 (per-bin
+        absorption opacity).  Afterwards step() takes I as [G, Ns, *n] and
+        returns R and G summed over the bins.  edges=None switches back to gray."""
+        import torch
+        if edges is None:
+            N.check(self._lib.rt_set_groups(self._ctx, 0, None, None, _stream()))
+            self.ng = 0
+            return
+        e = np.ascontiguousarray(np.asarray(edges, dtype=np.float64))
+        ng = e.size - 1
+        ka = _ptr(kappa_a_groups, "kappa_a_groups", torch.float64, ng * self.nc)
+        N.check(self._lib.rt_set_groups(self._ctx, int(ng), e.ctypes.data_as(C.c_void_p), ka, _stream()))
+        self.ng = ng
+        self._keep_groups = kappa_a_groups
+
     # -- hot path -------------------------------------------------------------
     def step(self, I, T, dt, nsteps=1, G=None, R=None):
         """Advance (I, T) in place by nsteps predictor-corrector steps; optional
         G [4, Nc] (4-force of the last step) and R [10, Nc] (moments of the new
         intensity) are filled in."""
         import torch
-        st = self._lib.rt_step(self._ctx, _ptr(I, "I", self.intensity_dtype, self.ns * self.nc),
+        st = self._lib.rt_step(self._ctx, _ptr(I, "I", self.intensity_dtype, max(self.ng, 1) * self.ns * self.nc),
                                _ptr(T, "T", torch.float64, self.nc), float(dt), int(nsteps),
                                _ptr(G, "G", torch.float64, 4 * self.nc, optional=True),
                                _ptr(R, "R", torch.float64, 10 * self.nc, optional=True), _stream())
@@ -149,7 +167,8 @@ class RTContext:
         """As step(), through rt_step_noalloc: the step scratch is the library's
         static per-device array (no device allocation in the call)."""
         import torch
-        st = self._lib.rt_step_noalloc(self._ctx, _ptr(I, "I", self.intensity_dtype, self.ns * self.nc),
+        st = self._lib.rt_step_noalloc(self._ctx, _ptr(I, "I", self.intensity_dtype,
+                                                       max(self.ng, 1) * self.ns * self.nc),
                                        _ptr(T, "T", torch.float64, self.nc), float(dt), int(nsteps),
                                        _ptr(G, "G", torch.float64, 4 * self.nc, optional=True),
                                        _ptr(R, "R", torch.float64, 10 * self.nc, optional=True), _stream())

@@ -22,9 +22,9 @@ RT_AREC_DONOR, RT_AREC_MAPR = 0, 1
 RT_FLAT, RT_KERR_SCHILD = 0, 1
 RT_OPAC_KIRCHHOFF_CONST, RT_OPAC_BREMS, RT_OPAC_FIXED_EMISSIVITY, RT_OPAC_BREMS_M3 = 0, 1, 2, 3
 RT_TETRAD, RT_COORD = 0, 1
-KERNELS = ["stage1", "stage2", "materialize", "moments", "adjoint", "angular"]
+KERNELS = ["stage1", "stage2", "materialize", "moments", "adjoint", "angular", "mg_solve"]
 
-EXPORTED = ["rt_init_grid", "rt_geodesic_grid", "rt_grid_info", "rt_set_metric", "rt_set_opacities", "rt_step",
+EXPORTED = ["rt_init_grid", "rt_geodesic_grid", "rt_grid_info", "rt_set_metric", "rt_set_opacities", "rt_set_groups", "rt_step",
             "rt_step_noalloc", "rt_moments", "rt_step_adjoint", "rt_step_adjoint_thermal", "rt_set_debug", "rt_kernel_times", "rt_newton_failures",
             "rt_destroy", "rt_last_error"]
 
@@ -64,6 +64,7 @@ def load():
         "rt_grid_info": ([P, C.POINTER(I), P, P, P], I),
         "rt_set_metric": ([P, I, D, D, D, C.POINTER(D)], I),
         "rt_set_opacities": ([P, C.POINTER(OpacityDesc), P], I),
+        "rt_set_groups": ([P, I, P, P, P], I),
         "rt_step": ([P, P, P, D, I, P, P, P], I),
         "rt_step_noalloc": ([P, P, P, D, I, P, P, P], I),
         "rt_moments": ([P, P, P, P, I, P], I),

@@ -20,7 +20,7 @@ COMMON = ["-O3", "-fPIC", "-std=c++17", f"--offload-arch={ARCH}",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-I", os.path.join(ROOT, "include"), "-Wall", "-Wno-unused-result"]
 SOURCES = ["grid.cpp", "kerr.cpp", "api.cpp", "kernels.hip", "stage.hip", "angular.hip", "adjoint.hip",
-           "noalloc.hip"]
+           "noalloc.hip", "multigroup.hip"]
 
 
 def hipcc():

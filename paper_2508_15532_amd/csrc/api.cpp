@@ -364,11 +364,16 @@ namespace {
 size_t round256(size_t b) { return (b + 255) / 256 * 256; }
 }  // namespace
 
+// doubles per cell of one lazy interaction map: (Q, abar, code) with a moving
+// fluid, (alpha, beta) at rest, (alpha, beta) per bin with frequency bins
+size_t map_words(const rt_ctx* c) { return std::max<size_t>(3, 2 * (size_t)c->ng); }
+
 size_t step_scratch_bytes(const rt_ctx* c) {
-  const size_t nc = (size_t)c->nc, ns = (size_t)c->ns;
-  size_t b = round256(ns * nc * c->elem) + 2 * round256(3 * nc * 8) + round256(nc * 8);
+  const size_t nc = (size_t)c->nc, ns = (size_t)c->ns, ng = (size_t)std::max(c->ng, 1);
+  size_t b = round256(ng * ns * nc * c->elem) + 2 * round256(map_words(c) * nc * 8) + round256(nc * 8);
   if (c->curved) b += round256(ns * nc * c->elem);
   if (c->mapr) b += round256(2 * ns * nc * c->elem);
+  if (c->ng) b += round256(ng * nc * 8);
   return b;
 }
 
@@ -380,13 +385,15 @@ StepScratch carve_step_scratch(const rt_ctx* c, void* base) {
     q += round256(bytes);
     return r;
   };
+  const size_t ng = (size_t)std::max(c->ng, 1);
   StepScratch w{};
-  w.Itil = take(ns * nc * c->elem);
-  w.mapA = (double*)take(3 * nc * 8);
-  w.mapB = (double*)take(3 * nc * 8);
+  w.Itil = take(ng * ns * nc * c->elem);
+  w.mapA = (double*)take(map_words(c) * nc * 8);
+  w.mapB = (double*)take(map_words(c) * nc * 8);
   w.Tstar = (double*)take(nc * 8);
   w.angD = c->curved ? take(ns * nc * c->elem) : nullptr;
   w.mp_grad = c->mapr ? take(2 * ns * nc * c->elem) : nullptr;
+  w.Emg = c->ng ? (double*)take(ng * nc * 8) : nullptr;
   return w;
 }
 
@@ -445,58 +452,114 @@ rt_status step_impl(rt_ctx* c, const StepScratch& ws, bool may_alloc, void* I, d
   auto run = [&](int kind, auto&& launch) -> hipError_t {
     return may_alloc ? timed(c, kind, stream, launch) : launch();
   };
-  const double* mapA = nullptr;  // the caller's I is materialised on entry
-  for (int k = 0; k < nsteps; ++k) {
-    const bool last = k == nsteps - 1;
-    // stage 1: fluxes of I^n, half step, interaction from T^n with opacities at T^n
-    a.h = 0.5 * dt;
-    p.Iflux_v = I;
-    p.mapF = mapA;
-    p.Ibase_v = nullptr;
-    p.mapB = nullptr;
-    p.Iout_v = ws.Itil;
-    p.mapO = ws.mapB;
-    p.Tstart = T;
-    p.Tcoef = T;
-    p.Tout = ws.Tstar;
-    if (c->curved)
-      RT_HIP(run(RT_K_ANGULAR, [&] { return launch_angular(c, I, ws.angD, ws.mp_grad, stream); }));
-    RT_HIP(run(RT_K_STAGE1, [&] { return launch_stage(c, a, p, false, stream, may_alloc); }));
-    const double* mapB = ws.mapB;
-    if (c->moving) {
-      RT_HIP(run(RT_K_MATERIALIZE, [&] {
-        return launch_materialize(c, ws.Itil, ws.mapB, a.h, nullptr, nullptr, stream);
-      }));
-      mapB = nullptr;
-    }
-    // stage 2: fluxes of I*, full step from I^n, energy balance from T^n, opacities at T*
-    a.h = dt;
-    p.Iflux_v = ws.Itil;
-    p.mapF = mapB;
-    p.Ibase_v = I;
-    p.mapB = mapA;
-    p.Iout_v = I;
-    p.mapO = ws.mapA;
-    p.Tstart = T;
-    p.Tcoef = ws.Tstar;
-    p.Tout = T;
-    if (c->curved)
-      RT_HIP(run(RT_K_ANGULAR, [&] { return launch_angular(c, ws.Itil, ws.angD, ws.mp_grad, stream); }));
-    RT_HIP(run(RT_K_STAGE2, [&] { return launch_stage(c, a, p, true, stream, may_alloc); }));
-    if (c->moving) {
-      RT_HIP(run(RT_K_MATERIALIZE, [&] {
-        return launch_materialize(c, I, ws.mapA, dt, last ? R_out : nullptr, last ? G_out : nullptr,
-                                  stream);
-      }));
-      mapA = nullptr;
-    } else {
+  if (c->ng && (!ws.Emg || !ws.Itil || !ws.mapA || !ws.mapB || !ws.Tstar || !c->d_ka_g))
+    return fail(RT_E_STATE, "rt_step: the frequency-bin scratch is not allocated");
+  if (c->ng) {
+    // frequency bins (at rest, flat): each stage transports every bin with its
+    // own opacity, the stage kernels leaving the per-bin E_- only; one solve
+    // per stage couples the bins through the temperature and writes the
+    // per-bin lazy maps
+    const size_t bin = (size_t)c->ns * c->nc * c->elem;
+    const long long nc = c->nc;
+    char* Ib = static_cast<char*>(I);
+    char* Jb = static_cast<char*>(ws.Itil);
+    const double* mapA = nullptr;  // the caller's I is materialised on entry
+    for (int k = 0; k < nsteps; ++k) {
+      a.h = 0.5 * dt;
+      for (int g = 0; g < c->ng; ++g) {
+        p.Iflux_v = Ib + g * bin;
+        p.mapF = mapA ? mapA + 2 * g * nc : nullptr;
+        p.Ibase_v = nullptr;
+        p.mapB = nullptr;
+        p.Iout_v = Jb + g * bin;
+        p.mapO = nullptr;
+        p.Tstart = T;
+        p.Tcoef = T;
+        p.Tout = nullptr;
+        p.ka = c->d_ka_g + g * nc;
+        p.sumE = ws.Emg + g * nc;
+        RT_HIP(run(RT_K_STAGE1, [&] { return launch_stage(c, a, p, false, stream, may_alloc); }));
+      }
+      RT_HIP(run(RT_K_MG_SOLVE, [&] { return launch_mg_solve(c, a.h, ws.Emg, T, ws.Tstar, ws.mapB, stream); }));
+      a.h = dt;
+      for (int g = 0; g < c->ng; ++g) {
+        p.Iflux_v = Jb + g * bin;
+        p.mapF = ws.mapB + 2 * g * nc;
+        p.Ibase_v = Ib + g * bin;
+        p.mapB = mapA ? mapA + 2 * g * nc : nullptr;
+        p.Iout_v = Ib + g * bin;
+        p.mapO = nullptr;
+        p.Tstart = T;
+        p.Tcoef = ws.Tstar;
+        p.Tout = nullptr;
+        p.ka = c->d_ka_g + g * nc;
+        p.sumE = ws.Emg + g * nc;
+        RT_HIP(run(RT_K_STAGE2, [&] { return launch_stage(c, a, p, true, stream, may_alloc); }));
+      }
+      RT_HIP(run(RT_K_MG_SOLVE, [&] { return launch_mg_solve(c, dt, ws.Emg, T, T, ws.mapA, stream); }));
       mapA = ws.mapA;
     }
-  }
-  if (mapA) {
-    // at rest the last interaction is still a lazy map: apply it, with the
-    // moments and the 4-force of the last step
-    RT_HIP(run(RT_K_MATERIALIZE, [&] { return launch_materialize(c, I, mapA, dt, R_out, G_out, stream); }));
+    if (mapA) {
+      // the bins' last maps, with R^(ab) and the 4-force summed over the bins
+      for (int g = 0; g < c->ng; ++g)
+        RT_HIP(run(RT_K_MATERIALIZE, [&] {
+          return launch_materialize(c, Ib + g * bin, mapA + 2 * g * nc, dt, R_out, G_out, stream, g > 0);
+        }));
+    }
+  } else {
+    const double* mapA = nullptr;  // the caller's I is materialised on entry
+    for (int k = 0; k < nsteps; ++k) {
+      const bool last = k == nsteps - 1;
+      // stage 1: fluxes of I^n, half step, interaction from T^n with opacities at T^n
+      a.h = 0.5 * dt;
+      p.Iflux_v = I;
+      p.mapF = mapA;
+      p.Ibase_v = nullptr;
+      p.mapB = nullptr;
+      p.Iout_v = ws.Itil;
+      p.mapO = ws.mapB;
+      p.Tstart = T;
+      p.Tcoef = T;
+      p.Tout = ws.Tstar;
+      if (c->curved)
+        RT_HIP(run(RT_K_ANGULAR, [&] { return launch_angular(c, I, ws.angD, ws.mp_grad, stream); }));
+      RT_HIP(run(RT_K_STAGE1, [&] { return launch_stage(c, a, p, false, stream, may_alloc); }));
+      const double* mapB = ws.mapB;
+      if (c->moving) {
+        RT_HIP(run(RT_K_MATERIALIZE, [&] {
+          return launch_materialize(c, ws.Itil, ws.mapB, a.h, nullptr, nullptr, stream);
+        }));
+        mapB = nullptr;
+      }
+      // stage 2: fluxes of I*, full step from I^n, energy balance from T^n, opacities at T*
+      a.h = dt;
+      p.Iflux_v = ws.Itil;
+      p.mapF = mapB;
+      p.Ibase_v = I;
+      p.mapB = mapA;
+      p.Iout_v = I;
+      p.mapO = ws.mapA;
+      p.Tstart = T;
+      p.Tcoef = ws.Tstar;
+      p.Tout = T;
+      if (c->curved)
+        RT_HIP(run(RT_K_ANGULAR, [&] { return launch_angular(c, ws.Itil, ws.angD, ws.mp_grad, stream); }));
+      RT_HIP(run(RT_K_STAGE2, [&] { return launch_stage(c, a, p, true, stream, may_alloc); }));
+      if (c->moving) {
+        RT_HIP(run(RT_K_MATERIALIZE, [&] {
+          return launch_materialize(c, I, ws.mapA, dt, last ? R_out : nullptr, last ? G_out : nullptr,
+                                    stream);
+        }));
+        mapA = nullptr;
+      } else {
+        mapA = ws.mapA;
+      }
+    }
+    if (mapA) {
+      // at rest the last interaction is still a lazy map: apply it, with the
+      // moments and the 4-force of the last step
+      RT_HIP(run(RT_K_MATERIALIZE, [&] { return launch_materialize(c, I, mapA, dt, R_out, G_out, stream); }));
+    }
   }
   if (c->debug & 1) {
     RT_HIP(launch_nonfinite(c, I, T, stream));
@@ -525,6 +588,8 @@ rt_status check_step_args(const rt_ctx* c, const char* who, const void* I, const
   if (nsteps < 0) return fail(RT_E_ARG, w + ": nsteps must be >= 0");
   if (!(dt > 0.0) || dt > c->dt_max * (1.0 + 1e-12))
     return fail(RT_E_ARG, w + ": need 0 < dt <= dt_max (" + std::to_string(c->dt_max) + ")");
+  if (c->ng && (c->curved || c->moving || c->opac.model != RT_OPAC_KIRCHHOFF_CONST))
+    return fail(RT_E_STATE, w + ": frequency bins need a fluid at rest and RT_OPAC_KIRCHHOFF_CONST");
   return RT_OK;
 }
 }  // namespace
@@ -746,6 +811,52 @@ rt_status rt_set_opacities(rt_ctx* c, const rt_opacity_desc* o, hipStream_t stre
   return RT_OK;
 }
 
+rt_status rt_set_groups(rt_ctx* c, int ng, const double* nu_edges_host, const double* kappa_a_groups,
+                        hipStream_t stream) {
+  if (!c) return fail(RT_E_ARG, "rt_set_groups: ctx is NULL");
+  if (!c->metric_set || !c->opac_set) return fail(RT_E_STATE, "rt_set_groups: set metric and opacities first");
+  if (ng < 0 || ng > RT_MAX_GROUPS)
+    return fail(RT_E_ARG, "rt_set_groups: ng must be in 0.." + std::to_string(RT_MAX_GROUPS));
+  if (ng > 0) {
+    if (c->curved || c->moving || c->opac.model != RT_OPAC_KIRCHHOFF_CONST)
+      return fail(RT_E_STATE,
+                  "rt_set_groups: frequency bins need the flat metric, a fluid at rest and RT_OPAC_KIRCHHOFF_CONST");
+    if (!nu_edges_host || !kappa_a_groups) return fail(RT_E_ARG, "rt_set_groups: NULL argument");
+    if (!aligned(kappa_a_groups)) return fail(RT_E_ARG, "rt_set_groups: kappa_a_groups must be 256-byte aligned");
+    if (!(nu_edges_host[0] >= 0.0) || std::isinf(nu_edges_host[0]))
+      return fail(RT_E_ARG, "rt_set_groups: the first edge must be finite and >= 0");
+    for (int g = 0; g < ng; ++g)
+      if (!(nu_edges_host[g + 1] > nu_edges_host[g]) || (g + 1 < ng && std::isinf(nu_edges_host[g + 1])))
+        return fail(RT_E_ARG, "rt_set_groups: edges must increase (only the last may be +inf)");
+  }
+  rt_status st = use_device(c);
+  if (st) return st;
+  const size_t nc = (size_t)c->nc, ns = (size_t)c->ns;
+  const int old = c->ng;
+  const size_t ngo = (size_t)std::max(old, 1), ngn = (size_t)std::max(ng, 1);
+  // the scratch of the old layout may still be in use by enqueued work
+  RT_HIP(hipStreamSynchronize(stream));
+  release(c->d_ka_g);
+  release(c->d_Emg);
+  c->ng = 0;
+  c->nu_edges.clear();
+  if (ngn != ngo || std::max<size_t>(3, 2 * (size_t)ng) != std::max<size_t>(3, 2 * (size_t)old)) {
+    release(c->d_Itil);
+    release(c->d_mapA);
+    release(c->d_mapB);
+  }
+  const size_t mw = std::max<size_t>(3, 2 * (size_t)ng);
+  if ((st = alloc(&c->d_Itil, ngn * ns * nc * c->elem)) || (st = alloc(&c->d_mapA, mw * nc * 8)) ||
+      (st = alloc(&c->d_mapB, mw * nc * 8)))
+    return st;
+  if (ng == 0) return RT_OK;
+  if ((st = alloc(&c->d_ka_g, (size_t)ng * nc * 8)) || (st = alloc(&c->d_Emg, (size_t)ng * nc * 8))) return st;
+  RT_HIP(hipMemcpyAsync(c->d_ka_g, kappa_a_groups, (size_t)ng * nc * 8, hipMemcpyDeviceToDevice, stream));
+  c->nu_edges.assign(nu_edges_host, nu_edges_host + ng + 1);
+  c->ng = ng;
+  return RT_OK;
+}
+
 rt_status rt_step(rt_ctx* c, void* I, double* T, double dt, int nsteps, double* G_out,
                   double* R_out, hipStream_t stream) {
   rt_status st = check_step_args(c, "rt_step", I, T, dt, nsteps, G_out, R_out);
@@ -758,6 +869,7 @@ rt_status rt_step(rt_ctx* c, void* I, double* T, double dt, int nsteps, double* 
   ws.Tstar = c->d_Tstar;
   ws.angD = c->d_angD;
   ws.mp_grad = c->d_mp_grad;
+  ws.Emg = c->d_Emg;
   return step_impl(c, ws, true, I, T, dt, nsteps, G_out, R_out, stream);
 }
 
@@ -801,6 +913,7 @@ rt_status rt_step_adjoint(rt_ctx* c, const void* I_n, const double* T_n, double 
     return fail(RT_E_ARG, "rt_step_adjoint: only the FIXED_EMISSIVITY model is differentiated");
   if (c->curved) return fail(RT_E_ARG, "rt_step_adjoint: only the flat metric is differentiated");
   if (c->moving) return fail(RT_E_ARG, "rt_step_adjoint: fluid must be at rest");
+  if (c->ng) return fail(RT_E_ARG, "rt_step_adjoint: frequency bins are not differentiated");
   if (!I_n || !T_n || !gI_np1 || !gI_n) return fail(RT_E_ARG, "rt_step_adjoint: NULL argument");
   if (!aligned(I_n) || !aligned(T_n) || !aligned(gI_np1) || !aligned(gI_n) ||
       (g_kappa_a && !aligned(g_kappa_a)) || (g_j && !aligned(g_j)))
@@ -829,6 +942,7 @@ rt_status rt_step_adjoint_thermal(rt_ctx* c, const void* I_n, const double* T_n,
     return fail(RT_E_ARG, "rt_step_adjoint_thermal: only the BREMS model (Method 2) is differentiated");
   if (c->curved) return fail(RT_E_ARG, "rt_step_adjoint_thermal: only the flat metric is differentiated");
   if (c->moving) return fail(RT_E_ARG, "rt_step_adjoint_thermal: fluid must be at rest");
+  if (c->ng) return fail(RT_E_ARG, "rt_step_adjoint_thermal: frequency bins are not differentiated");
   if (!I_n || !T_n || !gI_np1 || !gI_n || !gT_n) return fail(RT_E_ARG, "rt_step_adjoint_thermal: NULL argument");
   if (!aligned(I_n) || !aligned(T_n) || !aligned(gI_np1) || !aligned(gI_n) || !aligned(gT_n) ||
       (gT_np1 && !aligned(gT_np1)) || (g_kappa_a && !aligned(g_kappa_a)))
@@ -907,6 +1021,8 @@ void rt_destroy(rt_ctx* c) {
   release(c->d_mapA);
   release(c->d_mapB);
   release(c->d_Itil);
+  release(c->d_ka_g);
+  release(c->d_Emg);
   release(c->d_gA);
   release(c->d_gB);
   release(c->d_gC);

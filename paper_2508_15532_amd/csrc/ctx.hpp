@@ -76,6 +76,14 @@ struct rt_ctx {
   void* d_Itil = nullptr;      // [ns][nc] stage-1 output (I~ of the half step)
   double* d_mapA = nullptr;    // [3][nc] lazy interaction map of the state buffer
   double* d_mapB = nullptr;    // [3][nc] lazy interaction map of d_Itil
+  // frequency bins (rt_set_groups; 0: gray).  With bins the intensity and the
+  // per-stage scratch hold ng bin-major copies: d_Itil [ng][ns][nc], the lazy
+  // maps [ng][2][nc] (alpha, beta per bin; at least 3 nc), d_Emg [ng][nc] the
+  // per-bin E_- of the current stage
+  int ng = 0;
+  std::vector<double> nu_edges;  // [ng + 1]
+  double* d_ka_g = nullptr;      // [ng][nc] kappa_a per bin
+  double* d_Emg = nullptr;       // [ng][nc]
   double W0 = 0.0;             // sum of the weights
   double Wsum[10] = {0};       // sum_s w_s n^a n^b
   void* d_gA = nullptr;        // adjoint scratch [ns][nc] x 3
@@ -129,6 +137,7 @@ struct StepScratch {
   double* Tstar;    // [nc]
   void* angD;       // [ns][nc] transport type (curved only, else NULL)
   void* mp_grad;    // [ns][2][nc] transport type (MAPR only, else NULL)
+  double* Emg;      // [ng][nc] per-bin E_- (frequency bins only, else NULL)
 };
 // bytes of a context's step scratch laid out as 256-byte aligned parts, and
 // that layout carved from one base pointer
@@ -151,6 +160,11 @@ hipError_t launch_moments(rt_ctx* c, const void* I, double* R, double* J, hipStr
 // R^(ab) (tetrad) -> R^(mu nu) = e^mu_a e^nu_b R^(ab) in place (curved geometry)
 hipError_t launch_to_coord(rt_ctx* c, double* R, hipStream_t st);
 hipError_t launch_nonfinite(rt_ctx* c, const void* I, const double* T, hipStream_t st);
+// multi-group temperature solve and per-bin interaction maps of one stage
+// (multigroup.hip): from the per-bin E_- in c->d_Emg-like `Emg` [ng][nc],
+// writes T_out and map [ng][2][nc] (alpha, beta per bin)
+hipError_t launch_mg_solve(rt_ctx* c, double h, const double* Emg, const double* T_start, double* T_out,
+                           double* map, hipStream_t st);
 // one reverse step; gT_np1 (may be NULL) and gT_n are used by the
 // bremsstrahlung model only (gT_n is written, not accumulated)
 hipError_t launch_adjoint_step(rt_ctx* c, const void* I_n, const double* T_n, double dt,

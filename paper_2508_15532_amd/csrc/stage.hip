@@ -752,6 +752,11 @@ k_stage(StageArgs a, StagePtrs p) {
   for (int k = 0; k < TZ; ++k) {
     if (!valid[k]) continue;
     const long long c = own(k);
+    if (!MOVING && p.sumE) {
+      // one bin of a multi-group step: the solve couples all bins later
+      p.sumE[c] = acc[k][0];
+      continue;
+    }
     double aak, ask;
     opac(a, p.rho, p.Tcoef, p.ka, p.ks, c, aak, ask);
     const double ab = aak + ask, rrk = p.rho[c], T0k = p.Tstart[c];
@@ -808,7 +813,7 @@ k_materialize(long long nc, int ns, double h, const double* __restrict__ map, S*
               const double* __restrict__ uhat, const double* __restrict__ dirD,
               const double* __restrict__ w, const double* __restrict__ W16,
               double* __restrict__ Rout, double* __restrict__ Gout,
-              const double* __restrict__ nu0, int n3) {
+              const double* __restrict__ nu0, int n3, int acc) {
   long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= nc) return;
   if (!MOVING) {
@@ -837,9 +842,9 @@ k_materialize(long long nc, int ns, double h, const double* __restrict__ map, S*
       for (int m = 0; m < 4; ++m) g[m] += Ws[m] * (Iq - It);
     }
     if (Rout)
-      for (int m = 0; m < 10; ++m) Rout[m * nc + c] = R[m];
+      for (int m = 0; m < 10; ++m) Rout[m * nc + c] = (acc ? Rout[m * nc + c] : 0.0) + R[m];
     if (Gout)
-      for (int m = 0; m < 4; ++m) Gout[m * nc + c] = -g[m] / h;
+      for (int m = 0; m < 4; ++m) Gout[m * nc + c] = (acc ? Gout[m * nc + c] : 0.0) - g[m] / h;
     return;
   }
   const double Q = map[c], ab = map[nc + c];
@@ -900,7 +905,7 @@ template <typename S, bool MOM>
 __global__ void __launch_bounds__(256)
 k_materialize_pair(long long nc, int ns, double h, const double* __restrict__ map,
                    S* __restrict__ I, const double* __restrict__ W16,
-                   double* __restrict__ Rout, double* __restrict__ Gout) {
+                   double* __restrict__ Rout, double* __restrict__ Gout, int acc) {
   using V2 = typename std::conditional<std::is_same<S, float>::value, float2, double2>::type;
   const long long c = 2 * ((long long)blockIdx.x * blockDim.x + threadIdx.x);
   if (c >= nc) return;
@@ -949,13 +954,13 @@ k_materialize_pair(long long nc, int ns, double h, const double* __restrict__ ma
   if (MOM) {
     if (Rout)
       for (int m = 0; m < 10; ++m) {
-        Rout[m * nc + c] = R0[m];
-        Rout[m * nc + c + 1] = R1[m];
+        Rout[m * nc + c] = (acc ? Rout[m * nc + c] : 0.0) + R0[m];
+        Rout[m * nc + c + 1] = (acc ? Rout[m * nc + c + 1] : 0.0) + R1[m];
       }
     if (Gout)
       for (int m = 0; m < 4; ++m) {
-        Gout[m * nc + c] = -g0[m] / h;
-        Gout[m * nc + c + 1] = -g1[m] / h;
+        Gout[m * nc + c] = (acc ? Gout[m * nc + c] : 0.0) - g0[m] / h;
+        Gout[m * nc + c + 1] = (acc ? Gout[m * nc + c + 1] : 0.0) - g1[m] / h;
       }
   }
 }
@@ -1056,6 +1061,11 @@ hipError_t launch_tiled(rt_ctx* c, StageArgs a, const StagePtrs& p, bool stage2,
 
 hipError_t launch_stage(rt_ctx* c, const StageArgs& a, const StagePtrs& p, bool stage2,
                         hipStream_t st, bool may_alloc) {
+  // every pointer the kernel dereferences must be there: the interaction
+  // outputs unless only the per-cell sums are asked for (at rest)
+  if (!p.Iflux_v || !p.Iout_v || !p.rho || !p.Tcoef || (stage2 && !p.Ibase_v))
+    return hipErrorInvalidValue;
+  if (p.sumE ? (c->moving || c->curved) : (!p.Tout || !p.mapO || !p.Tstart)) return hipErrorInvalidValue;
   const bool mc = a.limiter == RT_LIM_MC;
   // the moving-fluid and curved forms carry more per-cell state (the fluid
   // velocity, advection weights, records): two cells per column (one in FP64)
@@ -1075,7 +1085,8 @@ hipError_t launch_stage(rt_ctx* c, const StageArgs& a, const StagePtrs& p, bool 
 }
 
 hipError_t launch_materialize(rt_ctx* c, void* I, const double* map, double h, double* R,
-                              double* G, hipStream_t st) {
+                              double* G, hipStream_t st, bool acc) {
+  const int ac = acc ? 1 : 0;
   dim3 grid((unsigned)((c->nc + 255) / 256)), block(256);
   if (!c->moving && c->nc % 2 == 0) {
     const dim3 g2((unsigned)((c->nc / 2 + 255) / 256));
@@ -1083,34 +1094,34 @@ hipError_t launch_materialize(rt_ctx* c, void* I, const double* map, double h, d
     if (c->fp32) {
       if (mom)
         hipLaunchKernelGGL((k_materialize_pair<float, true>), g2, block, 0, st, c->nc, c->ns, h, map,
-                           (float*)I, c->d_W16, R, G);
+                           (float*)I, c->d_W16, R, G, ac);
       else
         hipLaunchKernelGGL((k_materialize_pair<float, false>), g2, block, 0, st, c->nc, c->ns, h, map,
-                           (float*)I, c->d_W16, R, G);
+                           (float*)I, c->d_W16, R, G, ac);
     } else {
       if (mom)
         hipLaunchKernelGGL((k_materialize_pair<double, true>), g2, block, 0, st, c->nc, c->ns, h, map,
-                           (double*)I, c->d_W16, R, G);
+                           (double*)I, c->d_W16, R, G, ac);
       else
         hipLaunchKernelGGL((k_materialize_pair<double, false>), g2, block, 0, st, c->nc, c->ns, h, map,
-                           (double*)I, c->d_W16, R, G);
+                           (double*)I, c->d_W16, R, G, ac);
     }
     return hipGetLastError();
   }
   if (c->fp32) {
     if (c->moving)
       hipLaunchKernelGGL((k_materialize<float, true>), grid, block, 0, st, c->nc, c->ns, h, map,
-                         (float*)I, c->d_uhat, c->d_dir, c->d_w, c->d_W16, R, G, c->d_nu0, c->n[2]);
+                         (float*)I, c->d_uhat, c->d_dir, c->d_w, c->d_W16, R, G, c->d_nu0, c->n[2], ac);
     else
       hipLaunchKernelGGL((k_materialize<float, false>), grid, block, 0, st, c->nc, c->ns, h, map,
-                         (float*)I, c->d_uhat, c->d_dir, c->d_w, c->d_W16, R, G, c->d_nu0, c->n[2]);
+                         (float*)I, c->d_uhat, c->d_dir, c->d_w, c->d_W16, R, G, c->d_nu0, c->n[2], ac);
   } else {
     if (c->moving)
       hipLaunchKernelGGL((k_materialize<double, true>), grid, block, 0, st, c->nc, c->ns, h, map,
-                         (double*)I, c->d_uhat, c->d_dir, c->d_w, c->d_W16, R, G, c->d_nu0, c->n[2]);
+                         (double*)I, c->d_uhat, c->d_dir, c->d_w, c->d_W16, R, G, c->d_nu0, c->n[2], ac);
     else
       hipLaunchKernelGGL((k_materialize<double, false>), grid, block, 0, st, c->nc, c->ns, h, map,
-                         (double*)I, c->d_uhat, c->d_dir, c->d_w, c->d_W16, R, G, c->d_nu0, c->n[2]);
+                         (double*)I, c->d_uhat, c->d_dir, c->d_w, c->d_W16, R, G, c->d_nu0, c->n[2], ac);
   }
   return hipGetLastError();
 }

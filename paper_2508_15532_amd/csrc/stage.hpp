@@ -64,14 +64,20 @@ struct StagePtrs {
   // tile launch order: code = tx | ty << 10 | tz << 21 per position in the
   // order (NULL: x fastest, then y, then z)
   const unsigned* tile_order;
+  // at rest only: when set, the kernel writes each cell's E_- = sum_s w_s I~_s
+  // here ([nc]) instead of solving the interaction (Tout and mapO untouched);
+  // the multi-group solve then combines the bins
+  double* sumE;
 };
 
 // may_alloc = false: the call allocates nothing (the tile launch order is taken
 // from the context's cache when it matches, else tiles run in natural order)
 hipError_t launch_stage(rt_ctx* c, const StageArgs& a, const StagePtrs& p, bool stage2,
                         hipStream_t st, bool may_alloc = true);
+// acc: add the moments and the 4-force to R and G instead of overwriting them
+// (the bins of a multi-group step; at rest only)
 hipError_t launch_materialize(rt_ctx* c, void* I, const double* map, double h, double* R,
-                              double* G, hipStream_t st);
+                              double* G, hipStream_t st, bool acc = false);
 // angular flux divergence of I (curved geometry) into angD; MAPR keeps its
 // per-direction slopes in grad ([ns][2][nc])
 hipError_t launch_angular(rt_ctx* c, const void* I, void* angD, void* grad, hipStream_t st);

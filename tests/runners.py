@@ -124,8 +124,50 @@ def patch(field, center, radius):
     return field[..., idx[0][:, None, None], idx[1][None, :, None], idx[2][None, None, :]]
 
 
+def gpu_run_mg(wl, steps, precision="fp64", per_call=1, noalloc=False):
+    """Multi-group workload on the GPU: I [G, Ns, *n], T, R and G (summed over
+    the bins) of the last step; `per_call` steps per rt_step call."""
+    ctx = gpu_context(wl, precision)
+    dev = torch.device("cuda", 0)
+    kag = torch.as_tensor(np.ascontiguousarray(wl["kappa_a_groups"]), dtype=F64, device=dev)
+    ctx.set_groups(wl["group_edges"], kag)
+    G_ = kag.shape[0]
+    iso = torch.as_tensor(np.ascontiguousarray(wl["I0_iso_groups"]), dtype=F64, device=dev).reshape(G_, 1, -1)
+    I = iso.expand(G_, ctx.ns, ctx.nc).to(ctx.intensity_dtype).contiguous()
+    T = torch.as_tensor(np.ascontiguousarray(wl["T"]), dtype=F64, device=dev).reshape(-1).contiguous()
+    R = torch.zeros((10, ctx.nc), dtype=F64, device=dev)
+    Gf = torch.zeros((4, ctx.nc), dtype=F64, device=dev)
+    step = ctx.step_noalloc if noalloc else ctx.step
+    done = 0
+    while done < steps:
+        k = min(per_call, steps - done)
+        step(I, T, wl["dt"], k, G=Gf, R=R)
+        done += k
+    torch.cuda.synchronize()
+    shape = tuple(wl["n"])
+    out = dict(I=I.double().cpu().reshape((G_, ctx.ns) + shape), T=T.cpu().reshape(shape),
+               R=R.cpu().reshape((10,) + shape), G=Gf.cpu().reshape((4,) + shape),
+               fail=ctx.newton_failures())
+    ctx.close()
+    return out
+
+
+def oracle_run_mg(wl, steps):
+    """The oracle's multi-group steps; R and the 4-force of the last step's
+    second interaction, summed over the bins."""
+    from oracle import multigroup as mg
+    from oracle.setup import build_flat_mg
+    pb, ka, edges, I, T = build_flat_mg(wl)
+    g = pb.geo.grid
+    for _ in range(steps):
+        I, T, It = mg.step_mg(pb, ka, edges, I, T, wl["dt"])
+    R = mg.moments_mg(I, g.n, g.w)
+    Gf = -(R[0:4] - mg.moments_mg(It, g.n, g.w)[0:4]) / wl["dt"]
+    return dict(I=I, T=T, R=R, G=Gf, failed=sum(pb.failed))
+
+
 __all__ = ["W", "gpu_context", "gpu_initial", "gpu_run", "oracle_run", "rel_l2", "rel_max",
-           "moments_error", "J_of", "moving_fluid", "patch"]
+           "moments_error", "J_of", "moving_fluid", "patch", "gpu_run_mg", "oracle_run_mg"]
 
 
 def oracle_grad(wl, steps, I0, weights, limiter=0):
