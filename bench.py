@@ -45,7 +45,7 @@ FIELDS_B = 56
 R_B = 80
 
 
-def algorithmic_bytes(kind, elem, ns, nc):
+def algorithmic_bytes(kind, elem, ns, nc, ng=0):
     """Bytes a launch of each kernel must move at minimum, counted as the
     method's own transfers: intensities (stage 1 reads I^n and writes I*,
     stage 2 reads I* and I^n and writes I^(n+1)), the per-cell temperatures and
@@ -53,6 +53,20 @@ def algorithmic_bytes(kind, elem, ns, nc):
     re-reads and the angular-divergence scratch are implementation overhead and
     are not counted (they show in the measured traffic instead)."""
     cd = ns * nc
+    if ng:
+        # one bin of a multi-group step: the stage kernels read rho, kappa_s and
+        # the bin's kappa_a and write the bin's E_-; the solve reads E_- and
+        # kappa_a of every bin, rho, kappa_s and T_n and writes T and the
+        # per-bin maps; the materialisation accumulates R
+        if kind == "stage1":
+            return 2 * elem * cd + 32 * nc
+        if kind == "stage2":
+            return 3 * elem * cd + 32 * nc
+        if kind == "mg_solve":
+            return (32 * ng + 32) * nc
+        if kind == "materialize":
+            return 2 * elem * cd + 2 * R_B * nc
+        raise KeyError(kind)
     if kind == "stage1":
         return 2 * elem * cd + (16 + FIELDS_B) * nc
     if kind == "stage2":
@@ -68,11 +82,15 @@ def algorithmic_bytes(kind, elem, ns, nc):
     raise KeyError(kind)
 
 
-def step_algorithmic_bytes(elem, ns, nc):
+def step_algorithmic_bytes(elem, ns, nc, ng=0):
     """Per step, what the method itself must move: 5 intensity transfers per
     cell-direction (stage 1: I^n in, I* out; stage 2: I*, I^n in, I^(n+1) out),
     per cell the temperatures (5 x 8 B) and the fluid fields of both stages
-    (2 x 56 B), and R^(ab) of the new intensity (80 B)."""
+    (2 x 56 B), and R^(ab) of the new intensity (80 B).  With ng frequency
+    bins: 5 transfers per cell-direction-bin, per cell and stage rho, kappa_s,
+    T_n, T out and kappa_a of every bin, and R."""
+    if ng:
+        return 5 * elem * ng * ns * nc + (2 * (32 + 8 * ng) + R_B) * nc
     return 5 * elem * ns * nc + (40 + 2 * FIELDS_B + R_B) * nc
 
 
@@ -83,16 +101,25 @@ def make_inputs(wl, ctx, torch):
         return None if x is None else torch.as_tensor(x, dtype=torch.float64).reshape(-1).to(dev)
     rho, T, u = t(wl["rho"]), t(wl["T"]), t(wl.get("u"))
     ka, ks, j = t(wl.get("kappa_a")), t(wl.get("kappa_s")), t(wl.get("j"))
-    ctx.set_opacities(wl["model"], rho, u=u, kappa_a=ka, kappa_s=ks, j=j, gamma=wl["gamma"], C_a=wl["C_a"],
-                      C_s=wl["C_s"])
+    ctx.set_opacities(wl["model"], rho, u=u, kappa_a=ka, kappa_s=ks, j=j, gamma=wl["gamma"], C_a=wl.get("C_a", 1.0),
+                      C_s=wl.get("C_s", 1.0))
     if wl.get("metric") == "kerr_schild":
         I0 = torch.as_tensor(wl["I0_iso"], dtype=torch.float64).reshape(-1).to(dev)
     else:
         I0 = T ** 4 / (4 * math.pi)
     I = I0.reshape(1, -1).expand(ctx.ns, -1).to(ctx.intensity_dtype).contiguous()
+    kag = None
+    if wl.get("group_edges") is not None:
+        # frequency bins: I [G, Ns, Nc], each bin isotropic with its share
+        kag = torch.as_tensor(wl["kappa_a_groups"], dtype=torch.float64).reshape(len(wl["group_edges"]) - 1, -1)
+        kag = kag.to(dev).contiguous()
+        ctx.set_groups(wl["group_edges"], kag)
+        iso = torch.as_tensor(wl["I0_iso_groups"], dtype=torch.float64).reshape(ctx.ng, 1, -1).to(dev)
+        del I
+        I = iso.expand(ctx.ng, ctx.ns, ctx.nc).to(ctx.intensity_dtype).contiguous()
     R = torch.empty((10, ctx.nc), dtype=torch.float64, device=dev)
     G = torch.empty((4, ctx.nc), dtype=torch.float64, device=dev)
-    return (rho, u, G, ka, ks, j), I, T, R
+    return (rho, u, G, ka, ks, j, kag), I, T, R
 
 
 def make_context(wl, precision, P):
@@ -132,11 +159,11 @@ def run_form(wl, precision, steps, warmup, torch, P, per_call=False):
     ktimes = ctx.kernel_times()
     ctx.set_debug(0)
     ok = bool(torch.isfinite(R).all().item()) and bool(torch.isfinite(T).all().item())
-    ns, nc = ctx.ns, ctx.nc
+    ns, nc, ng = ctx.ns, ctx.nc, ctx.ng
     ctx.close()
     del I, T, R, G, keep
     torch.cuda.empty_cache()
-    return dict(wall=wall, ktimes=ktimes, ns=ns, nc=nc, finite=ok,
+    return dict(wall=wall, ktimes=ktimes, ns=ns, nc=nc, ng=ng, finite=ok,
                 elem=4 if precision == "fp32" else 8)
 
 
@@ -176,7 +203,7 @@ def roofline_block(wkey, r):
     dom = max(kt, key=lambda k: kt[k][1])
     launches, tot_ms = kt[dom]
     t = tot_ms / launches / 1e3
-    abytes = algorithmic_bytes(dom, r["elem"], r["ns"], r["nc"])
+    abytes = algorithmic_bytes(dom, r["elem"], r["ns"], r["nc"], r.get("ng", 0))
     hbm = abytes / t / 1e9
     cnt = counters_for(wkey, dom, r["elem"]) or {}
     traffic, valu = cnt.get("bytes"), cnt.get("valu_insts")
@@ -248,12 +275,12 @@ def run_moments(wl, precision, launches, warmup, torch, P):
 def step_frac(r, steps):
     """Fraction of the HBM peak that the method's own bytes per step
     (step_algorithmic_bytes) over the measured wall time per step amount to."""
-    return step_algorithmic_bytes(r["elem"], r["ns"], r["nc"]) * steps / r["wall"] / 1e9 / HBM_PEAK_GBS
+    return step_algorithmic_bytes(r["elem"], r["ns"], r["nc"], r.get("ng", 0)) * steps / r["wall"] / 1e9 / HBM_PEAK_GBS
 
 
 def line_entry(desc, wkey, r, steps):
     return {"workload": desc,
-            "value": r["ns"] * r["nc"] * steps / r["wall"],
+            "value": max(r.get("ng", 0), 1) * r["ns"] * r["nc"] * steps / r["wall"],
             "unit": "cell-direction updates/s",
             "steps": steps,
             "ms_per_step": 1e3 * r["wall"] / steps,
@@ -325,8 +352,8 @@ def run_adjoint(torch, P):
 
 def run_only(which, steps, warmup, torch, P, W):
     """One of the secondary lines: the Kerr-Schild torus with donor-cell or
-    MAPR angular states, the turbulent torus with 642 directions, or the
-    adjoint workload."""
+    MAPR angular states, the turbulent torus with 642 directions, the adjoint
+    workload, the emitting ball, or the multi-group workload."""
     if which == "torus":
         # curved geometry: the a = 0.9 Kerr-Schild torus, FP32 transport form
         print(f"bench: torus_ks fp32 256x128x64 x 162, {steps} steps", file=sys.stderr, flush=True)
@@ -353,6 +380,16 @@ def run_only(which, steps, warmup, torch, P, W):
     if which == "adjoint":
         print("bench: adjoint 64^3 x 162 fp32, 20 steps, checkpoints every 5", file=sys.stderr, flush=True)
         return run_adjoint(torch, P)
+    if which == "multigroup":
+        # frequency bins: the flat recipe with 4 bins (5.4 GB per FP32 intensity copy)
+        print(f"bench: multigroup fp32 128^3 x 162 x 4 bins, {steps} steps", file=sys.stderr, flush=True)
+        mw = W.multigroup_flat()
+        mr = run_form(mw, "fp32", steps, warmup, torch, P, per_call=True)
+        out = line_entry("flat 128^3 x 162 directions x 4 frequency bins [0,1,3,9,inf), lognormal rho, "
+                         "alpha^a_g = rho^2 (3, 1, 0.3, 0.1), alpha^s = rho, coupled temperature, FP32 "
+                         "transport", "multigroup128", mr, steps)
+        out["unit"] = "cell-direction-bin updates/s"
+        return out
     if which == "sphere":
         # the curved-coordinate validation workload at the torus line's size
         print(f"bench: bright sphere fp32 256x128x64 x 162, {steps} steps", file=sys.stderr, flush=True)
@@ -395,7 +432,9 @@ def main():
                     help="skip the curved-coordinate validation line (bright sphere 256x128x64 x 162, FP32)")
     ap.add_argument("--no-adjoint", action="store_true",
                     help="skip the adjoint line (64^3 x 162 FP32, 20 steps, checkpoints every 5)")
-    ap.add_argument("--only", choices=["torus", "mapr", "bigtorus", "adjoint", "sphere"],
+    ap.add_argument("--no-multigroup", action="store_true",
+                    help="skip the multi-group line (128^3 x 162 x 4 frequency bins, FP32)")
+    ap.add_argument("--only", choices=["torus", "mapr", "bigtorus", "adjoint", "sphere", "multigroup"],
                     help="run only that line (for profiling) and print it as one JSON object")
     ap.add_argument("--moments-only", action="store_true",
                     help="only time rt_moments on the 128^3 x 162 field (FP32 and FP64) and print it")
@@ -495,6 +534,8 @@ def main():
         out["adjoint"] = run_only("adjoint", 0, 0, torch, P, W)
     if not args.no_sphere:
         out["bright_sphere"] = run_only("sphere", min(args.steps, 10), 2, torch, P, W)
+    if not args.no_multigroup:
+        out["multigroup"] = run_only("multigroup", min(args.steps, 10), 2, torch, P, W)
     # the standalone moment contraction (inside rt_step R is formed in the
     # materialisation pass instead)
     print("bench: rt_moments 128^3 x 162", file=sys.stderr, flush=True)

@@ -480,7 +480,7 @@ rt_status step_impl(rt_ctx* c, const StepScratch& ws, bool may_alloc, void* I, d
         p.sumE = ws.Emg + g * nc;
         RT_HIP(run(RT_K_STAGE1, [&] { return launch_stage(c, a, p, false, stream, may_alloc); }));
       }
-      RT_HIP(run(RT_K_MG_SOLVE, [&] { return launch_mg_solve(c, a.h, ws.Emg, T, ws.Tstar, ws.mapB, stream); }));
+      RT_HIP(run(RT_K_MG_SOLVE, [&] { return launch_mg_solve(c, a.h, ws.Emg, T, T, ws.Tstar, ws.mapB, stream); }));
       a.h = dt;
       for (int g = 0; g < c->ng; ++g) {
         p.Iflux_v = Jb + g * bin;
@@ -496,7 +496,7 @@ rt_status step_impl(rt_ctx* c, const StepScratch& ws, bool may_alloc, void* I, d
         p.sumE = ws.Emg + g * nc;
         RT_HIP(run(RT_K_STAGE2, [&] { return launch_stage(c, a, p, true, stream, may_alloc); }));
       }
-      RT_HIP(run(RT_K_MG_SOLVE, [&] { return launch_mg_solve(c, dt, ws.Emg, T, T, ws.mapA, stream); }));
+      RT_HIP(run(RT_K_MG_SOLVE, [&] { return launch_mg_solve(c, dt, ws.Emg, T, ws.Tstar, T, ws.mapA, stream); }));
       mapA = ws.mapA;
     }
     if (mapA) {

@@ -161,10 +161,11 @@ hipError_t launch_moments(rt_ctx* c, const void* I, double* R, double* J, hipStr
 hipError_t launch_to_coord(rt_ctx* c, double* R, hipStream_t st);
 hipError_t launch_nonfinite(rt_ctx* c, const void* I, const double* T, hipStream_t st);
 // multi-group temperature solve and per-bin interaction maps of one stage
-// (multigroup.hip): from the per-bin E_- in c->d_Emg-like `Emg` [ng][nc],
-// writes T_out and map [ng][2][nc] (alpha, beta per bin)
-hipError_t launch_mg_solve(rt_ctx* c, double h, const double* Emg, const double* T_start, double* T_out,
-                           double* map, hipStream_t st);
+// (multigroup.hip): from the per-bin E_- in `Emg` [ng][nc], writes T_out and
+// map [ng][2][nc] (alpha, beta per bin); Newton starts from T_guess (may alias
+// T_start or T_out)
+hipError_t launch_mg_solve(rt_ctx* c, double h, const double* Emg, const double* T_start,
+                           const double* T_guess, double* T_out, double* map, hipStream_t st);
 // one reverse step; gT_np1 (may be NULL) and gT_n are used by the
 // bremsstrahlung model only (gT_n is written, not accumulated)
 hipError_t launch_adjoint_step(rt_ctx* c, const void* I_n, const double* T_n, double dt,

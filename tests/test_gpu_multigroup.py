@@ -57,6 +57,24 @@ def test_multigroup_matches_oracle(small_oracle, precision):
         assert rel_l2(g["R"][0], o["R"][0]) < 1e-5
 
 
+@pytest.mark.parametrize("edges", [(0.0, 0.5, 1.0, 2.0, 3.0, 6.0, math.inf),
+                                   (0.0, 0.3, 0.7, 1.0, 1.5, 2.0, 2.5, 3.5, 6.0, 12.0, math.inf)])
+def test_more_bins_match_oracle(edges):
+    """6 and 10 bins (the kernel keeps up to 8 bins' constants in registers and
+    re-reads them beyond), FP64, against the oracle."""
+    ng = len(edges) - 1
+    kap = tuple(3.0 * 0.6 ** k for k in range(ng))
+    wl = W.multigroup_flat(n=(3, 5, 66), generation=0, seed=25, edges=edges, kappa_groups=kap)
+    _say(f"multigroup {ng} bins: oracle")
+    o = oracle_run_mg(wl, 2)
+    _say(f"multigroup {ng} bins: GPU")
+    g = gpu_run_mg(wl, 2)
+    assert o["failed"] == 0 and g["fail"] == 0
+    for k in range(ng):
+        assert (g["I"][k] - o["I"][k]).abs().max() <= 1e-12 * o["I"][k].abs().max(), k
+    assert (g["T"] - o["T"]).abs().max() <= 1e-12 * o["T"].abs().max()
+
+
 def test_one_bin_is_the_gray_method1_step():
     """One bin [0, inf) with kappa_a,0 = kappa_a is the gray KIRCHHOFF_CONST
     step (Method 1): the Planck series and the bin solve against the quartic."""
