@@ -198,11 +198,18 @@ k_mg_solve(MgArgs a, const double* __restrict__ Emg, const double* __restrict__ 
         eval(x, F, dF);
         if (F > 0.0) hi = x;
         else lo = x;
-        double xn = x - F / dF;
+        const double step = F / dF;
+        double xn = x - step;
+        // converged: the Newton step is within the tolerance (tested before the
+        // bracket guard, which would replace a step onto the bracket's end)
+        if (fabs(step) <= a.rtol * x) {
+          if (xn >= lo && xn <= hi) x = xn;
+          ok = true;
+          break;
+        }
         if (!(xn > lo && xn < hi)) xn = 0.5 * (lo + hi);
-        const double dx = xn - x;
         x = xn;
-        if (fabs(dx) <= a.rtol * x || hi - lo <= a.rtol * x) {
+        if (hi - lo <= a.rtol * x) {
           ok = true;
           break;
         }

@@ -160,11 +160,17 @@ __device__ bool method3_root(double Y, double E0, double N, double as, double ab
     const double dF = -Y * g - 3.5 * e * N * p35 * ix - 0.5 * ab * A2 * N / sx;
     if (F > 0.0) lo = x;
     else hi = x;
-    double xn = x - F / dF;
+    const double step = F / dF;
+    double xn = x - step;
+    // converged: the Newton step is within the tolerance (tested before the
+    // bracket guard, which would replace a step onto the bracket's end)
+    if (fabs(step) <= rtol * x) {
+      T = (xn >= lo && xn <= hi) ? xn : x;
+      return true;
+    }
     if (!(xn > lo && xn < hi)) xn = 0.5 * (lo + hi);
-    const double dx = xn - x;
     x = xn;
-    if (fabs(dx) <= rtol * x || hi - lo <= rtol * x) {
+    if (hi - lo <= rtol * x) {
       T = x;
       return true;
     }
