@@ -27,60 +27,85 @@ constexpr int kBlock = 256;
 // ---------------------------------------------------------------------------
 typedef double d4 __attribute__((ext_vector_type(4)));
 
-template <typename S>
+// FP32 intensities, nc a multiple of 4, whole waves of cells only: lane (r, kq)
+// loads the four consecutive cells cell0 + 4r .. 4r + 3 of direction s0 + kq in
+// one 16-byte load, component m being row r of tile m (tile m's row i is cell
+// cell0 + 4i + m).  Batches of B four-direction steps; the loads of the next
+// batch are issued before the products of the current one, so every wave keeps
+// 2 B loads in flight while its matrix products run.  A kernel of its own so
+// that its register budget (and occupancy) is not set by the general path.
+template <int B>
 __global__ void __launch_bounds__(kBlock)
-k_moments(long long nc, int ns, const S* __restrict__ I, const double* __restrict__ W16,
-          double* __restrict__ R, double* __restrict__ J) {
+k_moments_f32(long long nc, int ns, const float* __restrict__ I, const double* __restrict__ W16,
+              double* __restrict__ R, double* __restrict__ J) {
   const int lane = threadIdx.x & 63;
   const long long wave = ((long long)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const long long cell0 = wave * 64;
+  if (cell0 + 64 > nc) return;
+  const int r = lane & 15, kq = lane >> 4;
+  d4 acc[4];
+#pragma unroll
+  for (int m = 0; m < 4; ++m) acc[m] = d4{0.0, 0.0, 0.0, 0.0};
+  const float* base = I + cell0 + 4 * r;
+  auto load = [&](int s00, float4* av, double* b) {
+#pragma unroll
+    for (int u = 0; u < B; ++u) {
+      const int s = s00 + 4 * u + kq;
+      b[u] = s < ns ? W16[s * 16 + r] : 0.0;
+      av[u] = s < ns ? *reinterpret_cast<const float4*>(base + (long long)s * nc) : float4{0.f, 0.f, 0.f, 0.f};
+    }
+  };
+  float4 av[B], an[B];
+  double b[B], bn[B];
+  load(0, av, b);
+  for (int s00 = 0; s00 < ns; s00 += 4 * B) {
+    const bool more = s00 + 4 * B < ns;
+    if (more) load(s00 + 4 * B, an, bn);
+#pragma unroll
+    for (int u = 0; u < B; ++u) {
+      acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64((double)av[u].x, b[u], acc[0], 0, 0, 0);
+      acc[1] = __builtin_amdgcn_mfma_f64_16x16x4f64((double)av[u].y, b[u], acc[1], 0, 0, 0);
+      acc[2] = __builtin_amdgcn_mfma_f64_16x16x4f64((double)av[u].z, b[u], acc[2], 0, 0, 0);
+      acc[3] = __builtin_amdgcn_mfma_f64_16x16x4f64((double)av[u].w, b[u], acc[3], 0, 0, 0);
+    }
+    if (more) {
+#pragma unroll
+      for (int u = 0; u < B; ++u) {
+        av[u] = an[u];
+        b[u] = bn[u];
+      }
+    }
+  }
+  // D[i][j] of tile m sits in lane j + 16 (i % 4), element i / 4: lane (r, kq)
+  // holds component r of cells cell0 + 4 (4e + kq) + m, m = 0..3 contiguous
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const long long cc = cell0 + 16 * e + 4 * kq;
+    if (r < 10) {
+      double* o = R + (long long)r * nc + cc;
+      *reinterpret_cast<d4*>(o) = d4{acc[0][e], acc[1][e], acc[2][e], acc[3][e]};
+    }
+    if (J && r == 0) {
+      const double q = 1.0 / (4.0 * kPi);
+      *reinterpret_cast<d4*>(J + cc) = d4{acc[0][e] * q, acc[1][e] * q, acc[2][e] * q, acc[3][e] * q};
+    }
+  }
+}
+
+// General path: FP64 intensities, and FP32 ones where k_moments_f32 does not
+// apply; waves start at cell first + 64 w.
+template <typename S>
+__global__ void __launch_bounds__(kBlock)
+k_moments(long long nc, int ns, const S* __restrict__ I, const double* __restrict__ W16,
+          double* __restrict__ R, double* __restrict__ J, long long first) {
+  const int lane = threadIdx.x & 63;
+  const long long wave = ((long long)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const long long cell0 = first + wave * 64;
   if (cell0 >= nc) return;
   const int r = lane & 15, kq = lane >> 4;
   d4 acc[4];
   for (int m = 0; m < 4; ++m) acc[m] = d4{0.0, 0.0, 0.0, 0.0};
   if constexpr (sizeof(S) == 4) {
-    if (cell0 + 64 <= nc && (nc & 3) == 0) {
-      // FP32 intensities, whole wave of cells: lane (r, kq) loads the four
-      // consecutive cells cell0 + 4r .. 4r + 3 of direction s0 + kq in one
-      // 16-byte load, component m being row r of tile m (tile m's row i is
-      // cell cell0 + 4i + m); batches of B four-direction steps, all loads of
-      // a batch issued before its products
-      constexpr int B = 4;
-      const float* base = (const float*)I + cell0 + 4 * r;
-      for (int s00 = 0; s00 < ns; s00 += 4 * B) {
-        float4 av[B];
-        double b[B];
-#pragma unroll
-        for (int u = 0; u < B; ++u) {
-          const int s = s00 + 4 * u + kq;
-          b[u] = s < ns ? W16[s * 16 + r] : 0.0;
-          av[u] = s < ns ? *reinterpret_cast<const float4*>(base + (long long)s * nc)
-                         : float4{0.f, 0.f, 0.f, 0.f};
-        }
-#pragma unroll
-        for (int u = 0; u < B; ++u) {
-          acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64((double)av[u].x, b[u], acc[0], 0, 0, 0);
-          acc[1] = __builtin_amdgcn_mfma_f64_16x16x4f64((double)av[u].y, b[u], acc[1], 0, 0, 0);
-          acc[2] = __builtin_amdgcn_mfma_f64_16x16x4f64((double)av[u].z, b[u], acc[2], 0, 0, 0);
-          acc[3] = __builtin_amdgcn_mfma_f64_16x16x4f64((double)av[u].w, b[u], acc[3], 0, 0, 0);
-        }
-      }
-      // D[i][j] of tile m sits in lane j + 16 (i % 4), element i / 4: lane (r, kq)
-      // holds component r of cells cell0 + 4 (4e + kq) + m, m = 0..3 contiguous
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const long long cc = cell0 + 16 * e + 4 * kq;
-        if (r < 10) {
-          double* o = R + (long long)r * nc + cc;
-          *reinterpret_cast<d4*>(o) = d4{acc[0][e], acc[1][e], acc[2][e], acc[3][e]};
-        }
-        if (J && r == 0) {
-          const double q = 1.0 / (4.0 * kPi);
-          *reinterpret_cast<d4*>(J + cc) = d4{acc[0][e] * q, acc[1][e] * q, acc[2][e] * q, acc[3][e] * q};
-        }
-      }
-      return;
-    }
     for (int s0 = 0; s0 < ns; s0 += 4) {
       const int s = s0 + kq;
       const double b = W16[s * 16 + r];  // W16 is zero-padded to a multiple of 4 rows
@@ -202,14 +227,22 @@ hipError_t launch_to_coord(rt_ctx* c, double* R, hipStream_t st) {
 }
 
 hipError_t launch_moments(rt_ctx* c, const void* I, double* R, double* J, hipStream_t st) {
-  long long waves = (c->nc + 63) / 64;
-  unsigned blocks = (unsigned)((waves * 64 + kBlock - 1) / kBlock);
-  if (c->fp32)
-    hipLaunchKernelGGL(k_moments<float>, dim3(blocks), dim3(kBlock), 0, st, c->nc, c->ns,
+  auto blocks_of = [](long long waves) { return (unsigned)((waves * 64 + kBlock - 1) / kBlock); };
+  if (!c->fp32) {
+    hipLaunchKernelGGL(k_moments<double>, dim3(blocks_of((c->nc + 63) / 64)), dim3(kBlock), 0, st, c->nc,
+                       c->ns, (const double*)I, c->d_W16, R, J, 0ll);
+    return hipGetLastError();
+  }
+  // FP32: whole waves through the 16-byte-load kernel when nc is a multiple of
+  // 4 (alignment of the loads), the ragged rest through the general path
+  const long long full = (c->nc % 4 == 0) ? c->nc / 64 : 0;
+  if (full > 0)
+    hipLaunchKernelGGL(k_moments_f32<4>, dim3(blocks_of(full)), dim3(kBlock), 0, st, c->nc, c->ns,
                        (const float*)I, c->d_W16, R, J);
-  else
-    hipLaunchKernelGGL(k_moments<double>, dim3(blocks), dim3(kBlock), 0, st, c->nc, c->ns,
-                       (const double*)I, c->d_W16, R, J);
+  const long long first = full * 64;
+  if (first < c->nc)
+    hipLaunchKernelGGL(k_moments<float>, dim3(blocks_of((c->nc - first + 63) / 64)), dim3(kBlock), 0, st,
+                       c->nc, c->ns, (const float*)I, c->d_W16, R, J, first);
   return hipGetLastError();
 }
 

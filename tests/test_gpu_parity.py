@@ -162,12 +162,14 @@ def test_degenerate_axes(shape):
 
 @pytest.mark.parametrize("gen", [0, 1, 2, 3])
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
-def test_moments_mfma(gen, precision):
+@pytest.mark.parametrize("n", [(3, 7, 11), (4, 7, 20)])
+def test_moments_mfma(gen, precision, n):
     """R^(ab) from the FP64 matrix cores vs the oracle's contraction, ragged
-    cell count (not a multiple of the 64-cell tile)."""
+    cell counts: 231 cells (not a multiple of 4: FP32 takes the general path)
+    and 560 (eight whole 64-cell waves through the FP32 16-byte-load kernel
+    and a 48-cell tail through the general one)."""
     from oracle import step as st
     from oracle.grid import GeodesicGrid
-    n = (3, 7, 11)
     G = GeodesicGrid(gen)
     I0 = W.random_intensity(G.ns, n, 50 + gen)
     ctx = gpu_context(W.brems_flat(n=n, generation=gen, seed=1), precision)
