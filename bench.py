@@ -16,6 +16,7 @@ import hashlib
 import json
 import math
 import os
+import re
 import sys
 import time
 
@@ -167,27 +168,44 @@ def run_form(wl, precision, steps, warmup, torch, P, per_call=False):
                 elem=4 if precision == "fp32" else 8)
 
 
-def sources_sha256():
-    """Hash of every kernel and host source of the library (sorted by name)."""
+# The sources each kernel kind is built from (its own file, the shared headers
+# and the host code that sets up its launch): a counter record stays valid
+# while these are unchanged.
+KERNEL_SOURCES = {
+    "stage1": ["stage.hip", "stage.hpp", "ctx.hpp", "api.cpp"],
+    "stage2": ["stage.hip", "stage.hpp", "ctx.hpp", "api.cpp"],
+    "materialize": ["stage.hip", "stage.hpp", "ctx.hpp", "api.cpp"],
+    "angular": ["angular.hip", "stage.hpp", "ctx.hpp", "api.cpp", "kerr.cpp"],
+    "moments": ["kernels.hip", "ctx.hpp", "api.cpp"],
+    "mg_solve": ["multigroup.hip", "ctx.hpp", "api.cpp"],
+    "adjoint": ["adjoint.hip", "stage.hip", "stage.hpp", "ctx.hpp", "api.cpp"],
+}
+
+
+def sources_sha256(names=None):
+    """Hash of the named library sources (default: every kernel and host
+    source), in sorted order."""
     h = hashlib.sha256()
-    for name in sorted(os.listdir(CSRC)):
-        if name.endswith((".hip", ".cpp", ".hpp")):
-            h.update(name.encode())
-            h.update(open(os.path.join(CSRC, name), "rb").read())
+    if names is None:
+        names = [n for n in os.listdir(CSRC) if n.endswith((".hip", ".cpp", ".hpp"))]
+    for name in sorted(set(names)):
+        h.update(name.encode())
+        h.update(open(os.path.join(CSRC, name), "rb").read())
     return h.hexdigest()
 
 
 def counters_for(wkey, kernel, elem):
     """Per-launch HBM bytes (rocprofv3 FETCH_SIZE + WRITE_SIZE, scaled by the
     plain-copy calibration) and VALU wave-instructions (SQ_INSTS_VALU) of
-    `kernel` on workload `wkey`, from the committed counter record, if it was
-    taken on the current library sources; else None."""
+    `kernel` on workload `wkey`, from the committed counter record, if the
+    record was taken on the current sources of that kernel; else None."""
     try:
         with open(TRAFFIC_FILE) as f:
             rec = json.load(f)
-        if rec.get("sources_sha256") != sources_sha256():
+        ent = rec["per_launch"].get(f"{wkey}/{kernel}_{'fp32' if elem == 4 else 'fp64'}")
+        if ent is None or ent.get("sources_sha256") != sources_sha256(KERNEL_SOURCES[kernel]):
             return None
-        return rec["per_launch"].get(f"{wkey}/{kernel}_{'fp32' if elem == 4 else 'fp64'}")
+        return ent
     except (OSError, KeyError, ValueError):
         return None
 
@@ -413,6 +431,92 @@ def accuracy_record():
     return rec
 
 
+# ---------------------------------------------------------------------------
+# rocprofv3 summaries: the kernel-trace statistics and the counters of the
+# same command (one counter set per run), per kernel, with the HBM bytes
+# scaled by the plain-copy calibration.  The per-launch figures of the hot-path
+# kernels are merged into profiles/traffic.json with the hash of their sources.
+# ---------------------------------------------------------------------------
+def _kernel_short(name):
+    name = name.replace("(anonymous namespace)::", "")
+    return re.sub(r"\(.*$", "", name).replace("void ", "").strip()
+
+
+def _kernel_kind(name):
+    """(kind, fp32?) of a library kernel, or (None, None)."""
+    f32 = "<float" in name or "_f32" in name
+    if "k_stage<" in name:
+        parts = [x.strip() for x in name.split("<", 1)[1].rstrip(">").split(",")]
+        return ("stage2" if parts[3] == "true" else "stage1"), parts[0] == "float"
+    for key, kind in (("k_materialize", "materialize"), ("k_moments", "moments"), ("k_angular", "angular"),
+                      ("k_mapr", "angular"), ("k_mg_solve", "mg_solve")):
+        if key in name:
+            return kind, f32
+    return None, None
+
+
+def _read_profile(d):
+    import csv
+    import glob
+    dur, cnt = {}, {}
+    for f in glob.glob(os.path.join(d, "**", "*kernel_stats.csv"), recursive=True):
+        for r in csv.DictReader(open(f)):
+            dur[_kernel_short(r["Name"])] = (int(r["Calls"]), float(r["AverageNs"]) / 1e6,
+                                             float(r["TotalDurationNs"]) / 1e6)
+    for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+        for r in csv.DictReader(open(f)):
+            cnt.setdefault(_kernel_short(r["Kernel_Name"]), {}).setdefault(r["Counter_Name"], []).append(
+                float(r["Counter_Value"]))
+    return dur, {k: {n: sum(v) / len(v) for n, v in c.items()} for k, c in cnt.items()}
+
+
+def summarize_profile(d, wkey, copy_dir, fp32_run):
+    """Text summary of one profiled command (directory d: its kernel trace and
+    counter runs) and the per-launch record of its library kernels."""
+    # the per-kind source hashes the profiled run printed (its sources, not the tree's now)
+    import glob
+    logged = None
+    for f in sorted(glob.glob(os.path.join(d, "*.log"))):
+        for line in open(f, errors="replace"):
+            if line.startswith("bench: sources "):
+                logged = json.loads(line[len("bench: sources "):])
+    if logged is None:
+        raise SystemExit(f"no 'bench: sources' line in the logs of {d}")
+    _, ccnt = _read_profile(copy_dir)
+    cp = ccnt["__amd_rocclr_copyBuffer"]
+    nbytes = float(1 << 30)
+    ff, wf = nbytes / (cp["FETCH_SIZE"] * 1024), nbytes / (cp["WRITE_SIZE"] * 1024)
+    dur, cnt = _read_profile(d)
+    lines = [f"HBM byte scaling from a plain 1 GiB device copy: FETCH_SIZE x {ff:.3f}, WRITE_SIZE x {wf:.3f}", ""]
+    per = {}
+    for k in sorted(set(dur) | set(cnt), key=lambda k: -dur.get(k, (0, 0, 0))[2]):
+        kind, f32 = _kernel_kind(k)
+        if kind is None and dur.get(k, (0, 0, 0))[2] < 0.01 * sum(v[2] for v in dur.values()):
+            continue  # small framework kernels
+        c = cnt.get(k, {})
+        lines.append(k)
+        if k in dur:
+            lines.append(f"    calls {dur[k][0]}  average {dur[k][1]:.4f} ms  total {dur[k][2]:.3f} ms")
+        for n in sorted(c):
+            lines.append(f"    {n:<16s} {c[n]:.5g}")
+        if "FETCH_SIZE" in c and "WRITE_SIZE" in c:
+            rb, wb = c["FETCH_SIZE"] * 1024 * ff, c["WRITE_SIZE"] * 1024 * wf
+            lines.append(f"    HBM bytes per launch (scaled): read {rb / 1e9:.4f} GB, written {wb / 1e9:.4f} GB")
+            if "SQ_INSTS_VALU" in c and k in dur:
+                busy = c["SQ_INSTS_VALU"] * VALU_CYCLES / (SIMDS * CLOCK_HZ * dur[k][1] / 1e3)
+                lines.append(f"    VALU busy {busy:.3f}, HBM busy {(rb + wb) / (dur[k][1] / 1e3) / 1e9 / HBM_PEAK_GBS:.3f}"
+                             " (of the trace's average duration)")
+            if kind:
+                key = f"{wkey}/{kind}_{'fp32' if (f32 or (kind == 'mg_solve' and fp32_run)) else 'fp64'}"
+                e = per.setdefault(key, {"bytes": 0.0, "valu_insts": 0.0, "avg_ms": 0.0,
+                                         "sources_sha256": logged[kind]})
+                e["bytes"] += rb + wb
+                e["valu_insts"] += c.get("SQ_INSTS_VALU", 0.0)
+                e["avg_ms"] += dur.get(k, (0, 0.0, 0))[1]
+        lines.append("")
+    return "\n".join(lines), per, (ff, wf)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -438,10 +542,35 @@ def main():
                     help="run only that line (for profiling) and print it as one JSON object")
     ap.add_argument("--moments-only", action="store_true",
                     help="only time rt_moments on the 128^3 x 162 field (FP32 and FP64) and print it")
+    ap.add_argument("--summarize-profile", metavar="DIR",
+                    help="print the summary of a profiled command's rocprofv3 output in DIR (no GPU) "
+                         "and merge its per-launch counters into profiles/traffic.json; needs "
+                         "--wkey and --copy-profile")
+    ap.add_argument("--wkey", help="workload key of --summarize-profile")
+    ap.add_argument("--copy-profile", metavar="DIR",
+                    help="rocprofv3 output of the --calibrate-copy run (FETCH_SIZE and WRITE_SIZE)")
+    ap.add_argument("--fp32-run", action="store_true", help="the profiled command ran the FP32 form")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy 5 times (the "
                          "reference kernel for scaling HBM byte counters) and exit")
     args = ap.parse_args()
+    if args.summarize_profile:
+        text, per, factors = summarize_profile(args.summarize_profile, args.wkey, args.copy_profile,
+                                               args.fp32_run)
+        print(text)
+        try:
+            with open(TRAFFIC_FILE) as f:
+                rec = json.load(f)
+        except (OSError, ValueError):
+            rec = {}
+        rec["fetch_factor"], rec["write_factor"] = factors
+        rec.setdefault("per_launch", {}).update(per)
+        with open(TRAFFIC_FILE, "w") as f:
+            json.dump(rec, f, indent=1, sort_keys=True)
+        return
+    # the sources of every kernel kind, for the counter records of profiled runs
+    print("bench: sources " + json.dumps({k: sources_sha256(v) for k, v in KERNEL_SOURCES.items()}),
+          file=sys.stderr, flush=True)
     if args.calibrate_copy:
         import torch
         src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")

@@ -37,7 +37,9 @@ def _errors(g, o):
 
 
 def _record(name, entry):
+    from bench import sources_sha256
     _RECORD[name] = entry
+    _RECORD["sources_sha256"] = sources_sha256()
     path = os.environ.get("RT_ACCURACY_OUT")
     if path:
         with open(path, "w") as f:
