@@ -284,12 +284,24 @@ k_src_adj(AdjArgs a, const S* __restrict__ It, const S* gI, S* gIt, const double
 }
 
 // ---------------------------------------------------------------------------
-// transport adjoint (gather form), one thread per cell, all directions:
+// transport adjoint (gather form), one thread per (cell, group of directions):
 //   out = add0 + add1 - h * D^T(gIt)  evaluated at the forward I_flux,
-// and the per-face sums dL/dtau_f = sum_s gF_f,s dF_f,s/dtau (stored per face:
-// the lower face of each cell, plus the upper boundary face of the last cell
-// of non-periodic axes, which is face index n of that axis).
+// and the per-face sums dL/dtau_f = sum_s gF_f,s dF_f,s/dtau over the group's
+// directions (stored per group and face: the lower face of each cell, plus the
+// upper boundary face of the last cell of non-periodic axes, which is face
+// index n of that axis).  The directions are split into gridDim.y groups so
+// that small grids still fill the GPU; the four faces a cell can feed along an
+// axis sit in fixed slots (registers), and positions wrap without division.
 // ---------------------------------------------------------------------------
+__device__ __forceinline__ int wrapp(int i, int n, bool periodic) {
+  if (periodic) {
+    while (i < 0) i += n;
+    while (i >= n) i -= n;
+    return i;
+  }
+  return i < 0 ? 0 : (i >= n ? n - 1 : i);
+}
+
 template <typename S, int LIM>
 __global__ void __launch_bounds__(256)
 k_tr_adj(AdjArgs a, const S* __restrict__ If, const S* __restrict__ gIt, const S* add0,
@@ -298,6 +310,8 @@ k_tr_adj(AdjArgs a, const S* __restrict__ If, const S* __restrict__ gIt, const S
          double* __restrict__ gtau) {
   const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= a.nc) return;
+  const int ng = gridDim.y, grp = blockIdx.y;
+  const int s_lo = (int)((long long)a.ns * grp / ng), s_hi = (int)((long long)a.ns * (grp + 1) / ng);
   const int n1 = a.n[0], n2 = a.n[1], n3 = a.n[2];
   const int ii[3] = {(int)(c / ((long long)n2 * n3)), (int)((c / n3) % n2), (int)(c % n3)};
   const long long st[3] = {(long long)n2 * n3, n3, 1};
@@ -306,38 +320,72 @@ k_tr_adj(AdjArgs a, const S* __restrict__ If, const S* __restrict__ gIt, const S
     cell_opac_T(a, rho, ka, ks, Tc, cell, r, aa, as);
     return aa + as;  // fluid at rest: u-hat^0 = 1
   };
+  double* gt = gtau + (long long)grp * 6 * a.nc;
   // Axis by axis: the faces f = m-1 .. m+2 (lower-face index, f in [0, n]) that
   // can hold this cell in their stencil, their weights (functions of the
-  // direction-independent tau, formed once per face), then all directions.
-  // The first axis writes out (with the additive terms), the others add to it.
-  // The thread owns the tau-gradient of its lower face (and of face n when it
-  // is the last cell of a non-periodic axis).
+  // direction-independent tau, formed once per face), then the group's
+  // directions.  The first axis writes out (with the additive terms), the
+  // others add to it.  The thread owns the tau-gradient of its lower face (and
+  // of face n when it is the last cell of a non-periodic axis).
   for (int ax = 0; ax < 3; ++ax) {
     const int na = ax == 0 ? n1 : (ax == 1 ? n2 : n3);
     const int m = ii[ax];
     const bool per = a.bc_lo[ax] == RT_BC_PERIODIC;
     const long long base = c - (long long)m * st[ax];
+    const long long sa = st[ax];
     const int nfaces = per ? na : na + 1;
+    // the faces' weights in the storage type (FP32 in the FP32 form), their tau
+    // derivatives only for the two faces the thread may own (slot 0: f = m,
+    // slot 1: f = n on a non-periodic axis)
     int fl[4];
-    Wts W[4];
-    int nf = 0;
-    for (int k = -1; k <= 2; ++k) {
-      int f = m + k;
-      if (per) f = wrapc(f, na, true);
-      if (f < 0 || f >= nfaces) continue;
-      bool dup = false;
-      for (int u = 0; u < nf; ++u) dup |= fl[u] == f;
-      if (dup) continue;
-      // the face between cells f-1 and f (stencil positions f-2 .. f+1, wrapped
-      // or clamped on use)
-      const long long cl = base + (long long)wrapc(f - 1, na, per) * st[ax];
-      const long long cr = base + (long long)wrapc(f, na, per) * st[ax];
-      W[nf] = weights(a.abar * 0.5 * (alpha_hat(cl) + alpha_hat(cr)) * a.dt);
-      fl[nf++] = f;
+    bool fv[4];
+    S wP[4], wQ[4], wU[4], wV[4];
+    double d0[4] = {0.0, 0.0, 0.0, 0.0}, d1[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      int f = m + u - 1;
+      if (per) f = wrapp(f, na, true);
+      bool ok = f >= 0 && f < nfaces;
+#pragma unroll
+      for (int v = 0; v < u; ++v) ok = ok && !(fv[v] && fl[v] == f);  // wrapped duplicates (na < 4)
+      fl[u] = f;
+      fv[u] = ok;
+      wP[u] = wQ[u] = wU[u] = wV[u] = S(0);
+      if (ok) {
+        // the face between cells f-1 and f (stencil positions f-2 .. f+1, wrapped
+        // or clamped on use)
+        const long long cl = base + (long long)wrapp(f - 1, na, per) * sa;
+        const long long cr = base + (long long)wrapp(f, na, per) * sa;
+        const Wts w = weights(a.abar * 0.5 * (alpha_hat(cl) + alpha_hat(cr)) * a.dt);
+        wP[u] = (S)w.P;
+        wQ[u] = (S)w.Q;
+        wU[u] = (S)w.U2;
+        wV[u] = (S)w.V2;
+        if (f == m) {
+          d0[0] = w.dP;
+          d0[1] = w.dQ;
+          d0[2] = w.dU2;
+          d0[3] = w.dV2;
+        } else if (!per && m == na - 1 && f == na) {
+          d1[0] = w.dP;
+          d1[1] = w.dQ;
+          d1[2] = w.dU2;
+          d1[3] = w.dV2;
+        }
+      }
     }
+    // offsets of the stencil positions m-3 .. m+3 (wrapped or clamped) from the
+    // axis line's first cell (32 bits: fewer than 2^29 cells); this cell is at mo
+    int po[7];
+#pragma unroll
+    for (int j = 0; j < 7; ++j) po[j] = wrapp(m - 3 + j, na, per) * (int)sa;
+    const int mo = m * (int)sa;
+    const bool zlo = !per && a.bc_lo[ax] == RT_BC_ZERO_INCOMING;
+    const bool zhi = !per && a.bc_hi[ax] == RT_BC_ZERO_INCOMING;
     double taug0 = 0.0, taug1 = 0.0;
-    for (int s = 0; s < a.ns; ++s) {
+    for (int s = s_lo; s < s_hi; ++s) {
       const long long off = (long long)s * a.nc;
+      const long long lb = off + base;  // this direction's axis line
       double acc = 0.0;
       if (ax == 0) {
         if (add0) acc += (double)add0[off + c];
@@ -347,65 +395,65 @@ k_tr_adj(AdjArgs a, const S* __restrict__ If, const S* __restrict__ gIt, const S
       }
       const double nu = dir[ax * a.ns + s];
       const bool pos = nu > 0.0;
-      // forward value at (possibly ghost) position p along the axis
-      auto val = [&](int p) -> double {
-        if (!per) {
-          if (p < 0 && a.bc_lo[ax] == RT_BC_ZERO_INCOMING && nu > 0.0) return 0.0;
-          if (p >= na && a.bc_hi[ax] == RT_BC_ZERO_INCOMING && nu < 0.0) return 0.0;
-        }
-        return (double)If[off + base + (long long)wrapc(p, na, per) * st[ax]];
+      // stencil position p = m - 3 + j: its forward value (zero for a zeroed
+      // ghost), whether it is this cell (zeroed ghosts feed nothing), and dL/dI~
+      // there (ghosts are not updated)
+      auto ghost0 = [&](int p) { return (p < 0 && zlo && pos) || (p >= na && zhi && !pos); };
+      auto val = [&](int j) -> double {
+        const int p = m - 3 + j;
+        return ghost0(p) ? 0.0 : (double)If[lb + po[j]];
       };
-      // does position p feed this cell (m)?  zeroed ghosts feed nothing
-      auto feeds = [&](int p) -> bool {
-        if (!per) {
-          if (p < 0 && a.bc_lo[ax] == RT_BC_ZERO_INCOMING && nu > 0.0) return false;
-          if (p >= na && a.bc_hi[ax] == RT_BC_ZERO_INCOMING && nu < 0.0) return false;
-        }
-        return wrapc(p, na, per) == m;
+      auto feeds = [&](int j) -> bool {
+        const int p = m - 3 + j;
+        return !ghost0(p) && po[j] == mo;
       };
-      auto gcell = [&](int p) -> double {  // dL/dI~ at cell p; ghosts are not updated
+      auto gcell = [&](int j) -> double {
+        const int p = m - 3 + j;
         if (!per && (p < 0 || p >= na)) return 0.0;
-        return (double)gIt[off + base + (long long)wrapc(p, na, per) * st[ax]];
+        return (double)gIt[lb + po[j]];
       };
-      for (int u = 0; u < nf; ++u) {
-        const int p0 = fl[u] - 2;  // stencil positions p0 .. p0+3
-        const int L = p0 + 1, R = p0 + 2;  // cells either side of the face
-        const double gF = (gcell(R) - gcell(L)) * a.inv_dx[ax] * a.h;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        if (!fv[u]) continue;
+        // face f = m + u - 1 (unwrapped): stencil positions f-2 .. f+1, i.e.
+        // window indices j0 .. j0+3 with j0 = u; cells either side j0+1, j0+2
+        const int j0 = u;
+        const double gF = (gcell(j0 + 2) - gcell(j0 + 1)) * a.inv_dx[ax] * a.h;
         if (gF == 0.0) continue;
-        const double v0 = val(p0), v1 = val(p0 + 1), v2 = val(p0 + 2), v3 = val(p0 + 3);
-        const Wts& Wf = W[u];
-        const double cP = pos ? Wf.P : Wf.Q, cQ = pos ? Wf.Q : Wf.P;
-        const double cU = pos ? Wf.U2 : Wf.V2, cV = pos ? Wf.V2 : Wf.U2;
+        const double v0 = val(j0), v1 = val(j0 + 1), v2 = val(j0 + 2), v3 = val(j0 + 3);
+        const double cP = pos ? wP[u] : wQ[u], cQ = pos ? wQ[u] : wP[u];
+        const double cU = pos ? wU[u] : wV[u], cV = pos ? wV[u] : wU[u];
         double a0, a1, b1, b2;
         const double hL = hslope<LIM>(v1 - v0, v2 - v1, a0, a1);
         const double hR = hslope<LIM>(v2 - v1, v3 - v2, b1, b2);
-        // dF/d(positions p0..p0+3)
+        // dF/d(positions f-2 .. f+1)
         const double g0 = nu * (-cU * a0);
         const double g1 = nu * (cP + cU * (a0 - a1) + cV * b1);
         const double g2 = nu * (cQ + cU * a1 - cV * (b1 - b2));
         const double g3 = nu * (-cV * b2);
         double contrib = 0.0;
-        if (feeds(p0)) contrib += g0;
-        if (feeds(p0 + 1)) contrib += g1;
-        if (feeds(p0 + 2)) contrib += g2;
-        if (feeds(p0 + 3)) contrib += g3;
+        if (feeds(j0)) contrib += g0;
+        if (feeds(j0 + 1)) contrib += g1;
+        if (feeds(j0 + 2)) contrib += g2;
+        if (feeds(j0 + 3)) contrib += g3;
         // F contributes -h F/dx to I~(L) and +h F/dx to I~(R): dL/dF = gF
         acc += gF * contrib;
         // tau-gradient of the faces this thread owns
         const int f = fl[u];
         const int slot = f == m ? 0 : ((!per && m == na - 1 && f == na) ? 1 : -1);
         if (slot >= 0) {
-          const double dcP = pos ? Wf.dP : Wf.dQ, dcQ = pos ? Wf.dQ : Wf.dP;
-          const double dcU = pos ? Wf.dU2 : Wf.dV2, dcV = pos ? Wf.dV2 : Wf.dU2;
+          const double* dw = slot == 0 ? d0 : d1;
+          const double dcP = pos ? dw[0] : dw[1], dcQ = pos ? dw[1] : dw[0];
+          const double dcU = pos ? dw[2] : dw[3], dcV = pos ? dw[3] : dw[2];
           const double dFdt = nu * (dcP * v1 + dcQ * v2 + dcU * hL - dcV * hR);
           (slot == 0 ? taug0 : taug1) += gF * dFdt;
         }
       }
       out[off + c] = (S)acc;
     }
-    // store per-face tau gradients: axis ax, lower face of this cell, and face n
-    gtau[(long long)ax * 2 * a.nc + c] = taug0;
-    gtau[(long long)ax * 2 * a.nc + a.nc + c] = taug1;
+    // this group's per-face tau gradients: axis ax, lower face of this cell, and face n
+    gt[(long long)ax * 2 * a.nc + c] = taug0;
+    gt[(long long)ax * 2 * a.nc + a.nc + c] = taug1;
   }
 }
 
@@ -416,7 +464,7 @@ k_tr_adj(AdjArgs a, const S* __restrict__ If, const S* __restrict__ gIt, const S
 // in for the ghost); dL/dkappa_a = rho dL/dalpha-hat.
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(256)
-k_tau_to_kappa(AdjArgs a, const double* __restrict__ gtau, const double* __restrict__ rho,
+k_tau_to_kappa(AdjArgs a, int ngroups, const double* __restrict__ gtau, const double* __restrict__ rho,
                const double* __restrict__ ka, const double* __restrict__ Tc, double* __restrict__ gka,
                double* __restrict__ gTc) {
   const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -430,16 +478,18 @@ k_tau_to_kappa(AdjArgs a, const double* __restrict__ gtau, const double* __restr
     const int m = ii[ax];
     const bool per = a.bc_lo[ax] == RT_BC_PERIODIC;
     const long long base = c - (long long)m * st[ax];
-    const double* lower = gtau + (long long)ax * 2 * a.nc;  // lower face of each cell
-    const double* upper = lower + a.nc;                      // face n, held by the last cell
+    // per direction group: the lower face of each cell, then face n (held by
+    // the last cell); the groups are summed in order
+    const long long up = m + 1 < na ? base + (long long)(m + 1) * st[ax] : (per ? base : -1);
+    double gl = 0.0;
+    double gu = 0.0;  // face between m and m+1
+    for (int grp = 0; grp < ngroups; ++grp) {
+      const double* lower = gtau + ((long long)grp * 3 + ax) * 2 * a.nc;
+      gl += lower[c];
+      gu += up >= 0 ? lower[up] : lower[a.nc + c];
+    }
     // face between m-1 and m (lower face of m): uses m once as its right cell,
     // and twice when m = 0 on a clamped axis (the ghost is a copy of m)
-    double gl = lower[c];
-    double gu;  // face between m and m+1
-    if (m + 1 < na)
-      gu = lower[base + (long long)(m + 1) * st[ax]];
-    else
-      gu = per ? lower[base] : upper[c];
     g += gl + gu;
     if (!per && m == 0) g += gl;       // left ghost copies cell 0
     if (!per && m == na - 1) g += gu;  // right ghost copies cell n-1
@@ -481,6 +531,8 @@ void reverse_step(rt_ctx* c, AdjArgs a, const void* I_n, const double* T_n, cons
                   const void* Z, const double* Tstar, const void* gI_np1, const double* gT_np1, void* gI_n,
                   double* gT_n, double* gTstar, double* g_ka, double* g_j, hipStream_t st) {
   const dim3 grid((unsigned)((c->nc + 255) / 256)), block(256);
+  const int ngr = adjoint_dir_groups(c);
+  const dim3 gridT((unsigned)((c->nc + 255) / 256), (unsigned)ngr);
   const bool brems = a.model == RT_OPAC_BREMS;
   S* gA = (S*)c->d_gA;  // dL/dI~ of stage 2 (also the base contribution to dL/dI^n)
   S* gB = (S*)c->d_gB;  // dL/dI*, then dL/dI~ of stage 1
@@ -492,10 +544,10 @@ void reverse_step(rt_ctx* c, AdjArgs a, const void* I_n, const double* T_n, cons
   else
     hipLaunchKernelGGL(k_src_adj<S>, grid, block, 0, st, a, (const S*)Z, (const S*)gI_np1, gA, c->d_rho,
                        c->d_ka, c->d_ks, c->d_j, c->d_w, g_ka, g_j);
-  hipLaunchKernelGGL((k_tr_adj<S, LIM>), grid, block, 0, st, a, (const S*)Y, (const S*)gA, (const S*)nullptr,
+  hipLaunchKernelGGL((k_tr_adj<S, LIM>), gridT, block, 0, st, a, (const S*)Y, (const S*)gA, (const S*)nullptr,
                      (const S*)nullptr, gB, c->d_dir, c->d_rho, c->d_ka, c->d_ks, Tstar, c->d_gcell);
   if (g_ka || brems)
-    hipLaunchKernelGGL(k_tau_to_kappa, grid, block, 0, st, a, c->d_gcell, c->d_rho, c->d_ka, Tstar, g_ka,
+    hipLaunchKernelGGL(k_tau_to_kappa, grid, block, 0, st, a, ngr, c->d_gcell, c->d_rho, c->d_ka, Tstar, g_ka,
                        gTstar);
   // stage 1: h = dt/2, T_start = T_coef = T^n (dL/dT* arrives as dL/dT_out)
   a.h = 0.5 * a.dt;
@@ -505,12 +557,24 @@ void reverse_step(rt_ctx* c, AdjArgs a, const void* I_n, const double* T_n, cons
   else
     hipLaunchKernelGGL(k_src_adj<S>, grid, block, 0, st, a, (const S*)X, (const S*)gB, gB, c->d_rho, c->d_ka,
                        c->d_ks, c->d_j, c->d_w, g_ka, g_j);
-  hipLaunchKernelGGL((k_tr_adj<S, LIM>), grid, block, 0, st, a, (const S*)I_n, (const S*)gB, (const S*)gA,
+  hipLaunchKernelGGL((k_tr_adj<S, LIM>), gridT, block, 0, st, a, (const S*)I_n, (const S*)gB, (const S*)gA,
                      (const S*)gB, (S*)gI_n, c->d_dir, c->d_rho, c->d_ka, c->d_ks, T_n, c->d_gcell);
   if (g_ka || brems)
-    hipLaunchKernelGGL(k_tau_to_kappa, grid, block, 0, st, a, c->d_gcell, c->d_rho, c->d_ka, T_n, g_ka, gT_n);
+    hipLaunchKernelGGL(k_tau_to_kappa, grid, block, 0, st, a, ngr, c->d_gcell, c->d_rho, c->d_ka, T_n, g_ka,
+                       gT_n);
 }
 }  // namespace
+
+int adjoint_dir_groups(const rt_ctx* c) {
+  // enough (cell, direction group) threads to fill the GPU, about 16384 waves,
+  // in at most 4 groups (each group re-forms the face weights; 4 and 8 groups
+  // measured alike at 64^3, 32 slower)
+  const long long waves = (c->nc + 63) / 64;
+  long long g = (16384 + waves - 1) / waves;
+  if (g > 4) g = 4;
+  if (g > c->ns) g = c->ns;
+  return (int)(g < 1 ? 1 : g);
+}
 
 hipError_t launch_adjoint_step(rt_ctx* c, const void* I_n, const double* T_n, double dt,
                                const void* gI_np1, const double* gT_np1, void* gI_n, double* gT_n,

@@ -923,7 +923,7 @@ rt_status rt_step_adjoint(rt_ctx* c, const void* I_n, const double* T_n, double 
   if (st) return st;
   const size_t bytes = (size_t)c->ns * c->nc * c->elem;
   if ((st = alloc(&c->d_gA, bytes)) || (st = alloc(&c->d_gB, bytes)) || (st = alloc(&c->d_gC, bytes)) ||
-      (st = alloc(&c->d_gD, bytes)) || (st = alloc(&c->d_gcell, 6 * (size_t)c->nc * 8)) ||
+      (st = alloc(&c->d_gD, bytes)) || (st = alloc(&c->d_gcell, 6 * (size_t)adjoint_dir_groups(c) * c->nc * 8)) ||
       (st = alloc(&c->d_gT, 2 * (size_t)c->nc * 8)))
     return st;
   RT_HIP(timed(c, RT_K_ADJOINT, stream, [&] {
@@ -954,7 +954,7 @@ rt_status rt_step_adjoint_thermal(rt_ctx* c, const void* I_n, const double* T_n,
   if (st) return st;
   const size_t bytes = (size_t)c->ns * c->nc * c->elem;
   if ((st = alloc(&c->d_gA, bytes)) || (st = alloc(&c->d_gB, bytes)) || (st = alloc(&c->d_gC, bytes)) ||
-      (st = alloc(&c->d_gD, bytes)) || (st = alloc(&c->d_gcell, 6 * (size_t)c->nc * 8)) ||
+      (st = alloc(&c->d_gD, bytes)) || (st = alloc(&c->d_gcell, 6 * (size_t)adjoint_dir_groups(c) * c->nc * 8)) ||
       (st = alloc(&c->d_gT, 2 * (size_t)c->nc * 8)))
     return st;
   RT_HIP(timed(c, RT_K_ADJOINT, stream, [&] {

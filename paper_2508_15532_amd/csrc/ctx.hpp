@@ -90,7 +90,7 @@ struct rt_ctx {
   void* d_gB = nullptr;
   void* d_gC = nullptr;
   void* d_gD = nullptr;
-  double* d_gcell = nullptr;   // adjoint per-face tau gradients [3][2][nc]
+  double* d_gcell = nullptr;   // adjoint per-face tau gradients [groups][3][2][nc]
   double* d_gT = nullptr;      // adjoint: dL/dT* and a stage-2 temperature scratch [2][nc]
   unsigned long long* d_count = nullptr;  // [0] interaction failures, [1] non-finite
   // launch order of the stage kernel's tiles (bricks of tiles that run together),
@@ -166,6 +166,9 @@ hipError_t launch_nonfinite(rt_ctx* c, const void* I, const double* T, hipStream
 // T_start or T_out)
 hipError_t launch_mg_solve(rt_ctx* c, double h, const double* Emg, const double* T_start,
                            const double* T_guess, double* T_out, double* map, hipStream_t st);
+// direction groups of the transport adjoint (its per-face scratch holds
+// groups x 6 nc doubles)
+int adjoint_dir_groups(const rt_ctx* c);
 // one reverse step; gT_np1 (may be NULL) and gT_n are used by the
 // bremsstrahlung model only (gT_n is written, not accumulated)
 hipError_t launch_adjoint_step(rt_ctx* c, const void* I_n, const double* T_n, double dt,
