@@ -168,17 +168,17 @@ def run_form(wl, precision, steps, warmup, torch, P, per_call=False):
                 elem=4 if precision == "fp32" else 8)
 
 
-# The sources each kernel kind is built from (its own file, the shared headers
-# and the host code that sets up its launch): a counter record stays valid
-# while these are unchanged.
+# The device code of each kernel kind: its own source file and the header that
+# defines its arguments.  A counter record stays valid while these are unchanged.
 KERNEL_SOURCES = {
-    "stage1": ["stage.hip", "stage.hpp", "ctx.hpp", "api.cpp"],
-    "stage2": ["stage.hip", "stage.hpp", "ctx.hpp", "api.cpp"],
-    "materialize": ["stage.hip", "stage.hpp", "ctx.hpp", "api.cpp"],
-    "angular": ["angular.hip", "stage.hpp", "ctx.hpp", "api.cpp", "kerr.cpp"],
-    "moments": ["kernels.hip", "ctx.hpp", "api.cpp"],
-    "mg_solve": ["multigroup.hip", "ctx.hpp", "api.cpp"],
-    "adjoint": ["adjoint.hip", "stage.hip", "stage.hpp", "ctx.hpp", "api.cpp"],
+    "stage1": ["stage.hip", "stage.hpp"],
+    "stage2": ["stage.hip", "stage.hpp"],
+    "materialize": ["stage.hip", "stage.hpp"],
+    "angular": ["angular.hip", "stage.hpp"],
+    "moments": ["kernels.hip"],
+    "mg_solve": ["multigroup.hip"],
+    "adjoint": ["adjoint.hip", "stage.hip", "stage.hpp"],
+    "tr_adjoint": ["adjoint.hip"],
 }
 
 
@@ -356,6 +356,15 @@ def run_adjoint(torch, P):
     ctx.close()
     t = ms_adj / n_adj / 1e3
     ab = algorithmic_bytes("adjoint", 4, ns, nc)
+    # the dominant kernel of a reverse step (the transport adjoint, two launches
+    # per step) from the committed counters of the current adjoint sources
+    cnt = counters_for("adjoint64", "tr_adjoint", 4) or {}
+    dom = None
+    if cnt:
+        ts = cnt["avg_ms"] / 1e3
+        dom = {"kernel": "k_tr_adj", "avg_ms": cnt["avg_ms"], "traffic": cnt["bytes"],
+               "hbm_busy": cnt["bytes"] / ts / 1e9 / HBM_PEAK_GBS,
+               "valu_busy": cnt["valu_insts"] * VALU_CYCLES / (SIMDS * CLOCK_HZ * ts)}
     return {"workload": "flat 64^3 x 162, FP32, fixed emissivity, 20 steps, checkpoints every 5, "
                         "gradient of the +x outgoing flux w.r.t. kappa_a and j",
             "forward_backward_ms": wall * 1e3,
@@ -364,7 +373,7 @@ def run_adjoint(torch, P):
             "adjoint_cell_direction_steps_per_s": ns * nc / t,
             "roofline": {"bound": "hbm", "achieved": ab / t / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": ab / t / 1e9 / HBM_PEAK_GBS, "traffic": None, "kernel": "adjoint step",
-                         "algorithmic_bytes": ab},
+                         "algorithmic_bytes": ab, "dominant_kernel": dom},
             "finite": bool(torch.isfinite(g).all().item())}
 
 
@@ -449,7 +458,7 @@ def _kernel_kind(name):
         parts = [x.strip() for x in name.split("<", 1)[1].rstrip(">").split(",")]
         return ("stage2" if parts[3] == "true" else "stage1"), parts[0] == "float"
     for key, kind in (("k_materialize", "materialize"), ("k_moments", "moments"), ("k_angular", "angular"),
-                      ("k_mapr", "angular"), ("k_mg_solve", "mg_solve")):
+                      ("k_mapr", "angular"), ("k_mg_solve", "mg_solve"), ("k_tr_adj", "tr_adjoint")):
         if key in name:
             return kind, f32
     return None, None
@@ -506,8 +515,10 @@ def summarize_profile(d, wkey, copy_dir, fp32_run):
                 busy = c["SQ_INSTS_VALU"] * VALU_CYCLES / (SIMDS * CLOCK_HZ * dur[k][1] / 1e3)
                 lines.append(f"    VALU busy {busy:.3f}, HBM busy {(rb + wb) / (dur[k][1] / 1e3) / 1e9 / HBM_PEAK_GBS:.3f}"
                              " (of the trace's average duration)")
-            if kind:
-                key = f"{wkey}/{kind}_{'fp32' if (f32 or (kind == 'mg_solve' and fp32_run)) else 'fp64'}"
+            if kind and kind not in logged:
+                lines.append(f"    (no source hash of kind {kind} in the run's log: no per-launch record)")
+            elif kind:
+                key = f"{wkey}/{kind}_{'fp32' if (f32 or (kind in ('mg_solve', 'tr_adjoint') and fp32_run)) else 'fp64'}"
                 e = per.setdefault(key, {"bytes": 0.0, "valu_insts": 0.0, "avg_ms": 0.0,
                                          "sources_sha256": logged[kind]})
                 e["bytes"] += rb + wb
