@@ -284,14 +284,23 @@ k_src_adj(AdjArgs a, const S* __restrict__ It, const S* gI, S* gIt, const double
 }
 
 // ---------------------------------------------------------------------------
-// transport adjoint (gather form), one thread per (cell, group of directions):
-//   out = add0 + add1 - h * D^T(gIt)  evaluated at the forward I_flux,
-// and the per-face sums dL/dtau_f = sum_s gF_f,s dF_f,s/dtau over the group's
-// directions (stored per group and face: the lower face of each cell, plus the
-// upper boundary face of the last cell of non-periodic axes, which is face
-// index n of that axis).  The directions are split into gridDim.y groups so
-// that small grids still fill the GPU; the four faces a cell can feed along an
-// axis sit in fixed slots (registers), and positions wrap without division.
+// transport adjoint, one axis per launch: the axis's part of -h D^T(gIt),
+// evaluated at the forward I_flux, written to out with add0 + add1 (init) or
+// added to out (the later axes), and the per-face
+// sums dL/dtau_f = sum_s gF_f,s dF_f,s/dtau of this axis over a group of
+// directions.  A thread owns a segment of up to L consecutive cells m0 ..
+// m0+L-1 of one line along the axis and forms each face f = m0-1 .. m0+L+1 once
+// per direction (stencil positions f-2 .. f+1, unwrapped), adding each face's
+// derivative at position p to the cell p of the segment.  That is the gather
+// over the faces m-1 .. m+2 of every cell m written face-major, so wrapped
+// duplicates of a face on short periodic lines are counted as the stencils
+// count them.  Ghost positions outside a clamped (non-periodic) axis feed its
+// edge cell unless the boundary zeroes them for this direction's sign.
+// Lines run along x (i3) for consecutive lanes on the y and z axes, segments
+// along x on the x axis.  The thread owns the tau-gradient of its cells' lower
+// faces, and of face n at the end of a non-periodic line (stored at the last
+// cell's second slot); the direction groups (gridDim.y) write partials that
+// k_tau_to_kappa sums in order.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int wrapp(int i, int n, bool periodic) {
   if (periodic) {
@@ -302,158 +311,159 @@ __device__ __forceinline__ int wrapp(int i, int n, bool periodic) {
   return i < 0 ? 0 : (i >= n ? n - 1 : i);
 }
 
-template <typename S, int LIM>
+template <typename S, int LIM, int L>
 __global__ void __launch_bounds__(256)
-k_tr_adj(AdjArgs a, const S* __restrict__ If, const S* __restrict__ gIt, const S* add0,
+k_tr_adj(AdjArgs a, int ax, int init, const S* __restrict__ If, const S* __restrict__ gIt, const S* add0,
          const S* add1, S* out, const double* __restrict__ dir, const double* __restrict__ rho,
          const double* __restrict__ ka, const double* __restrict__ ks, const double* __restrict__ Tc,
          double* __restrict__ gtau) {
-  const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= a.nc) return;
+  const int n1 = a.n[0], n2 = a.n[1], n3 = a.n[2];
+  const int na = ax == 0 ? n1 : (ax == 1 ? n2 : n3);
+  const long long sa = ax == 0 ? (long long)n2 * n3 : (ax == 1 ? (long long)n3 : 1ll);
+  const long long nlines = a.nc / na;
+  const int nseg = (na + L - 1) / L;
+  const long long tid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (tid >= nlines * nseg) return;
+  long long l;
+  int seg;
+  if (ax == 2) {
+    l = tid / nseg;
+    seg = (int)(tid % nseg);
+  } else {
+    l = tid % nlines;
+    seg = (int)(tid / nlines);
+  }
+  const long long base = ax == 0 ? l : (ax == 1 ? (l / n3) * (long long)n2 * n3 + (l % n3) : l * n3);
+  const int m0 = seg * L;
+  const int ncell = min(L, na - m0);
+  const bool first = m0 == 0, last = m0 + ncell == na;
+  const bool per = a.bc_lo[ax] == RT_BC_PERIODIC;
+  const bool zlo = !per && a.bc_lo[ax] == RT_BC_ZERO_INCOMING;
+  const bool zhi = !per && a.bc_hi[ax] == RT_BC_ZERO_INCOMING;
   const int ng = gridDim.y, grp = blockIdx.y;
   const int s_lo = (int)((long long)a.ns * grp / ng), s_hi = (int)((long long)a.ns * (grp + 1) / ng);
-  const int n1 = a.n[0], n2 = a.n[1], n3 = a.n[2];
-  const int ii[3] = {(int)(c / ((long long)n2 * n3)), (int)((c / n3) % n2), (int)(c % n3)};
-  const long long st[3] = {(long long)n2 * n3, n3, 1};
   auto alpha_hat = [&](long long cell) {
     double r, aa, as;
     cell_opac_T(a, rho, ka, ks, Tc, cell, r, aa, as);
     return aa + as;  // fluid at rest: u-hat^0 = 1
   };
-  double* gt = gtau + (long long)grp * 6 * a.nc;
-  // Axis by axis: the faces f = m-1 .. m+2 (lower-face index, f in [0, n]) that
-  // can hold this cell in their stencil, their weights (functions of the
-  // direction-independent tau, formed once per face), then the group's
-  // directions.  The first axis writes out (with the additive terms), the
-  // others add to it.  The thread owns the tau-gradient of its lower face (and
-  // of face n when it is the last cell of a non-periodic axis).
-  for (int ax = 0; ax < 3; ++ax) {
-    const int na = ax == 0 ? n1 : (ax == 1 ? n2 : n3);
-    const int m = ii[ax];
-    const bool per = a.bc_lo[ax] == RT_BC_PERIODIC;
-    const long long base = c - (long long)m * st[ax];
-    const long long sa = st[ax];
-    const int nfaces = per ? na : na + 1;
-    // the faces' weights in the storage type (FP32 in the FP32 form), their tau
-    // derivatives only for the two faces the thread may own (slot 0: f = m,
-    // slot 1: f = n on a non-periodic axis)
-    int fl[4];
-    bool fv[4];
-    S wP[4], wQ[4], wU[4], wV[4];
-    double d0[4] = {0.0, 0.0, 0.0, 0.0}, d1[4] = {0.0, 0.0, 0.0, 0.0};
+  // offsets (from the line's first cell, 32 bits: fewer than 2^29 cells) of the
+  // positions m0-3 .. m0+L+2, wrapped or clamped
+  int po[L + 6];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      int f = m + u - 1;
-      if (per) f = wrapp(f, na, true);
-      bool ok = f >= 0 && f < nfaces;
+  for (int j = 0; j < L + 6; ++j) po[j] = wrapp(m0 - 3 + j, na, per) * (int)sa;
+  // faces f = m0-1+q, q = 0 .. L+2: weights in the storage type; tau derivatives
+  // for the faces the thread owns, q = 1 .. L (lower faces) and L+1 (face n)
+  constexpr int NF = L + 3;
+  const int nfaces = per ? na : na + 1;
+  bool fv[NF];
+  S wP[NF], wQ[NF], wU[NF], wV[NF];
+  double dP[L + 1], dQ[L + 1], dU[L + 1], dV[L + 1];
 #pragma unroll
-      for (int v = 0; v < u; ++v) ok = ok && !(fv[v] && fl[v] == f);  // wrapped duplicates (na < 4)
-      fl[u] = f;
-      fv[u] = ok;
-      wP[u] = wQ[u] = wU[u] = wV[u] = S(0);
-      if (ok) {
-        // the face between cells f-1 and f (stencil positions f-2 .. f+1, wrapped
-        // or clamped on use)
-        const long long cl = base + (long long)wrapp(f - 1, na, per) * sa;
-        const long long cr = base + (long long)wrapp(f, na, per) * sa;
-        const Wts w = weights(a.abar * 0.5 * (alpha_hat(cl) + alpha_hat(cr)) * a.dt);
-        wP[u] = (S)w.P;
-        wQ[u] = (S)w.Q;
-        wU[u] = (S)w.U2;
-        wV[u] = (S)w.V2;
-        if (f == m) {
-          d0[0] = w.dP;
-          d0[1] = w.dQ;
-          d0[2] = w.dU2;
-          d0[3] = w.dV2;
-        } else if (!per && m == na - 1 && f == na) {
-          d1[0] = w.dP;
-          d1[1] = w.dQ;
-          d1[2] = w.dU2;
-          d1[3] = w.dV2;
+  for (int q = 0; q < NF; ++q) {
+    const int f = m0 - 1 + q;
+    fv[q] = per || (f >= 0 && f < nfaces);
+    wP[q] = wQ[q] = wU[q] = wV[q] = S(0);
+    if (q >= 1 && q <= L + 1) dP[q - 1] = dQ[q - 1] = dU[q - 1] = dV[q - 1] = 0.0;
+    if (!fv[q] || q > ncell + 2) continue;
+    const long long cl = base + (long long)wrapp(f - 1, na, per) * sa;
+    const long long cr = base + (long long)wrapp(f, na, per) * sa;
+    const Wts w = weights(a.abar * 0.5 * (alpha_hat(cl) + alpha_hat(cr)) * a.dt);
+    wP[q] = (S)w.P;
+    wQ[q] = (S)w.Q;
+    wU[q] = (S)w.U2;
+    wV[q] = (S)w.V2;
+    if (q >= 1 && q <= L + 1) {
+      dP[q - 1] = w.dP;
+      dQ[q - 1] = w.dQ;
+      dU[q - 1] = w.dU2;
+      dV[q - 1] = w.dV2;
+    }
+  }
+  const bool owns_n = !per && last;  // face n, q = ncell + 1
+  double tg[L + 1];
+#pragma unroll
+  for (int q = 0; q <= L; ++q) tg[q] = 0.0;
+  const double hdx = a.inv_dx[ax] * a.h;
+  for (int s = s_lo; s < s_hi; ++s) {
+    const long long lb = (long long)s * a.nc + base;  // this direction's line
+    const double nu = dir[ax * a.ns + s];
+    const bool pos = nu > 0.0;
+    // forward values at positions m0-3+j (zero for a zeroed ghost) and dL/dI~ at
+    // m0-2+j (zero at ghosts: they are not updated)
+    double v[L + 6], gc[L + 4];
+#pragma unroll
+    for (int j = 0; j < L + 6; ++j) {
+      const int p = m0 - 3 + j;
+      const bool z = (p < 0 && zlo && pos) || (p >= na && zhi && !pos);
+      v[j] = (z || p > m0 + ncell + 2) ? 0.0 : (double)If[lb + po[j]];
+    }
+#pragma unroll
+    for (int j = 0; j < L + 4; ++j) {
+      const int p = m0 - 2 + j;
+      gc[j] = ((!per && (p < 0 || p >= na)) || p > m0 + ncell + 1) ? 0.0 : (double)gIt[lb + po[j + 1]];
+    }
+    double acc[L];
+#pragma unroll
+    for (int i = 0; i < L; ++i) acc[i] = 0.0;
+#pragma unroll
+    for (int q = 0; q < NF; ++q) {
+      if (!fv[q] || q > ncell + 2) continue;
+      // face f = m0-1+q between positions f-1 and f (gc[q], gc[q+1]); F
+      // contributes -h F/dx to I~(f-1) and +h F/dx to I~(f): dL/dF = gF
+      const double gF = (gc[q + 1] - gc[q]) * hdx;
+      if (gF == 0.0) continue;
+      const double v0 = v[q], v1 = v[q + 1], v2 = v[q + 2], v3 = v[q + 3];
+      const double cP = pos ? wP[q] : wQ[q], cQ = pos ? wQ[q] : wP[q];
+      const double cU = pos ? wU[q] : wV[q], cV = pos ? wV[q] : wU[q];
+      double a0, a1, b1, b2;
+      const double hL = hslope<LIM>(v1 - v0, v2 - v1, a0, a1);
+      const double hR = hslope<LIM>(v2 - v1, v3 - v2, b1, b2);
+      // gF dF/d(positions f-2 .. f+1)
+      double g[4];
+      g[0] = gF * nu * (-cU * a0);
+      g[1] = gF * nu * (cP + cU * (a0 - a1) + cV * b1);
+      g[2] = gF * nu * (cQ + cU * a1 - cV * (b1 - b2));
+      g[3] = gF * nu * (-cV * b2);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int i = q - 3 + k;  // position m0 + i
+        if (i >= 0 && i < ncell) acc[i] += g[k];
+        if (!per) {
+          const int p = m0 + i;
+          if (p < 0 && first && !(zlo && pos)) acc[0] += g[k];
+          if (p >= na && last && !(zhi && !pos)) acc[ncell - 1] += g[k];
         }
       }
+      if ((q >= 1 && q <= ncell) || (owns_n && q == ncell + 1)) {
+        const double dcP = pos ? dP[q - 1] : dQ[q - 1], dcQ = pos ? dQ[q - 1] : dP[q - 1];
+        const double dcU = pos ? dU[q - 1] : dV[q - 1], dcV = pos ? dV[q - 1] : dU[q - 1];
+        tg[q - 1] += gF * nu * (dcP * v1 + dcQ * v2 + dcU * hL - dcV * hR);
+      }
     }
-    // offsets of the stencil positions m-3 .. m+3 (wrapped or clamped) from the
-    // axis line's first cell (32 bits: fewer than 2^29 cells); this cell is at mo
-    int po[7];
 #pragma unroll
-    for (int j = 0; j < 7; ++j) po[j] = wrapp(m - 3 + j, na, per) * (int)sa;
-    const int mo = m * (int)sa;
-    const bool zlo = !per && a.bc_lo[ax] == RT_BC_ZERO_INCOMING;
-    const bool zhi = !per && a.bc_hi[ax] == RT_BC_ZERO_INCOMING;
-    double taug0 = 0.0, taug1 = 0.0;
-    for (int s = s_lo; s < s_hi; ++s) {
-      const long long off = (long long)s * a.nc;
-      const long long lb = off + base;  // this direction's axis line
-      double acc = 0.0;
-      if (ax == 0) {
-        if (add0) acc += (double)add0[off + c];
-        if (add1) acc += (double)add1[off + c];
+    for (int i = 0; i < L; ++i) {
+      if (i >= ncell) break;
+      const long long o = lb + (long long)(m0 + i) * sa;
+      double x = acc[i];
+      if (init) {
+        if (add0) x += (double)add0[o];
+        if (add1) x += (double)add1[o];
       } else {
-        acc = (double)out[off + c];
+        x += (double)out[o];
       }
-      const double nu = dir[ax * a.ns + s];
-      const bool pos = nu > 0.0;
-      // stencil position p = m - 3 + j: its forward value (zero for a zeroed
-      // ghost), whether it is this cell (zeroed ghosts feed nothing), and dL/dI~
-      // there (ghosts are not updated)
-      auto ghost0 = [&](int p) { return (p < 0 && zlo && pos) || (p >= na && zhi && !pos); };
-      auto val = [&](int j) -> double {
-        const int p = m - 3 + j;
-        return ghost0(p) ? 0.0 : (double)If[lb + po[j]];
-      };
-      auto feeds = [&](int j) -> bool {
-        const int p = m - 3 + j;
-        return !ghost0(p) && po[j] == mo;
-      };
-      auto gcell = [&](int j) -> double {
-        const int p = m - 3 + j;
-        if (!per && (p < 0 || p >= na)) return 0.0;
-        return (double)gIt[lb + po[j]];
-      };
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        if (!fv[u]) continue;
-        // face f = m + u - 1 (unwrapped): stencil positions f-2 .. f+1, i.e.
-        // window indices j0 .. j0+3 with j0 = u; cells either side j0+1, j0+2
-        const int j0 = u;
-        const double gF = (gcell(j0 + 2) - gcell(j0 + 1)) * a.inv_dx[ax] * a.h;
-        if (gF == 0.0) continue;
-        const double v0 = val(j0), v1 = val(j0 + 1), v2 = val(j0 + 2), v3 = val(j0 + 3);
-        const double cP = pos ? wP[u] : wQ[u], cQ = pos ? wQ[u] : wP[u];
-        const double cU = pos ? wU[u] : wV[u], cV = pos ? wV[u] : wU[u];
-        double a0, a1, b1, b2;
-        const double hL = hslope<LIM>(v1 - v0, v2 - v1, a0, a1);
-        const double hR = hslope<LIM>(v2 - v1, v3 - v2, b1, b2);
-        // dF/d(positions f-2 .. f+1)
-        const double g0 = nu * (-cU * a0);
-        const double g1 = nu * (cP + cU * (a0 - a1) + cV * b1);
-        const double g2 = nu * (cQ + cU * a1 - cV * (b1 - b2));
-        const double g3 = nu * (-cV * b2);
-        double contrib = 0.0;
-        if (feeds(j0)) contrib += g0;
-        if (feeds(j0 + 1)) contrib += g1;
-        if (feeds(j0 + 2)) contrib += g2;
-        if (feeds(j0 + 3)) contrib += g3;
-        // F contributes -h F/dx to I~(L) and +h F/dx to I~(R): dL/dF = gF
-        acc += gF * contrib;
-        // tau-gradient of the faces this thread owns
-        const int f = fl[u];
-        const int slot = f == m ? 0 : ((!per && m == na - 1 && f == na) ? 1 : -1);
-        if (slot >= 0) {
-          const double* dw = slot == 0 ? d0 : d1;
-          const double dcP = pos ? dw[0] : dw[1], dcQ = pos ? dw[1] : dw[0];
-          const double dcU = pos ? dw[2] : dw[3], dcV = pos ? dw[3] : dw[2];
-          const double dFdt = nu * (dcP * v1 + dcQ * v2 + dcU * hL - dcV * hR);
-          (slot == 0 ? taug0 : taug1) += gF * dFdt;
-        }
-      }
-      out[off + c] = (S)acc;
+      out[o] = (S)x;
     }
-    // this group's per-face tau gradients: axis ax, lower face of this cell, and face n
-    gt[(long long)ax * 2 * a.nc + c] = taug0;
-    gt[(long long)ax * 2 * a.nc + a.nc + c] = taug1;
+  }
+  // this group's per-face tau gradients of this axis: the lower face of each
+  // cell of the segment, and face n in the last cell's second slot
+  double* gt = gtau + ((long long)grp * 3 + ax) * 2 * a.nc;
+#pragma unroll
+  for (int i = 0; i < L; ++i) {
+    if (i >= ncell) break;
+    const long long c = base + (long long)(m0 + i) * sa;
+    gt[c] = tg[i];
+    if (owns_n && i == ncell - 1) gt[a.nc + c] = tg[ncell];
   }
 }
 
@@ -524,6 +534,17 @@ k_apply_map(long long nc, int ns, const double* __restrict__ map, const S* __res
 }  // namespace
 
 namespace {
+// cells per thread segment of the transport adjoint
+constexpr int kAdjSeg = 4;
+
+// threads of one axis pass of the transport adjoint: lines x segments, and the
+// direction groups
+dim3 tr_grid(const rt_ctx* c, int ax, int groups) {
+  const long long na = c->n[ax];
+  const long long threads = c->nc / na * ((na + kAdjSeg - 1) / kAdjSeg);
+  return dim3((unsigned)((threads + 255) / 256), (unsigned)groups);
+}
+
 // reverse of one step given the forward states X = I~ (stage 1), Y = I*,
 // Z = I~ (stage 2) and T* (stage 1's temperature); see the kernels above
 template <typename S, int LIM>
@@ -532,7 +553,6 @@ void reverse_step(rt_ctx* c, AdjArgs a, const void* I_n, const double* T_n, cons
                   double* gT_n, double* gTstar, double* g_ka, double* g_j, hipStream_t st) {
   const dim3 grid((unsigned)((c->nc + 255) / 256)), block(256);
   const int ngr = adjoint_dir_groups(c);
-  const dim3 gridT((unsigned)((c->nc + 255) / 256), (unsigned)ngr);
   const bool brems = a.model == RT_OPAC_BREMS;
   S* gA = (S*)c->d_gA;  // dL/dI~ of stage 2 (also the base contribution to dL/dI^n)
   S* gB = (S*)c->d_gB;  // dL/dI*, then dL/dI~ of stage 1
@@ -544,8 +564,10 @@ void reverse_step(rt_ctx* c, AdjArgs a, const void* I_n, const double* T_n, cons
   else
     hipLaunchKernelGGL(k_src_adj<S>, grid, block, 0, st, a, (const S*)Z, (const S*)gI_np1, gA, c->d_rho,
                        c->d_ka, c->d_ks, c->d_j, c->d_w, g_ka, g_j);
-  hipLaunchKernelGGL((k_tr_adj<S, LIM>), gridT, block, 0, st, a, (const S*)Y, (const S*)gA, (const S*)nullptr,
-                     (const S*)nullptr, gB, c->d_dir, c->d_rho, c->d_ka, c->d_ks, Tstar, c->d_gcell);
+  for (int ax = 0; ax < 3; ++ax)
+    hipLaunchKernelGGL((k_tr_adj<S, LIM, kAdjSeg>), tr_grid(c, ax, ngr), block, 0, st, a, ax, ax == 0 ? 1 : 0,
+                       (const S*)Y, (const S*)gA, (const S*)nullptr, (const S*)nullptr, gB, c->d_dir, c->d_rho,
+                       c->d_ka, c->d_ks, Tstar, c->d_gcell);
   if (g_ka || brems)
     hipLaunchKernelGGL(k_tau_to_kappa, grid, block, 0, st, a, ngr, c->d_gcell, c->d_rho, c->d_ka, Tstar, g_ka,
                        gTstar);
@@ -557,8 +579,10 @@ void reverse_step(rt_ctx* c, AdjArgs a, const void* I_n, const double* T_n, cons
   else
     hipLaunchKernelGGL(k_src_adj<S>, grid, block, 0, st, a, (const S*)X, (const S*)gB, gB, c->d_rho, c->d_ka,
                        c->d_ks, c->d_j, c->d_w, g_ka, g_j);
-  hipLaunchKernelGGL((k_tr_adj<S, LIM>), gridT, block, 0, st, a, (const S*)I_n, (const S*)gB, (const S*)gA,
-                     (const S*)gB, (S*)gI_n, c->d_dir, c->d_rho, c->d_ka, c->d_ks, T_n, c->d_gcell);
+  for (int ax = 0; ax < 3; ++ax)
+    hipLaunchKernelGGL((k_tr_adj<S, LIM, kAdjSeg>), tr_grid(c, ax, ngr), block, 0, st, a, ax, ax == 0 ? 1 : 0,
+                       (const S*)I_n, (const S*)gB, (const S*)gA, (const S*)gB, (S*)gI_n, c->d_dir, c->d_rho,
+                       c->d_ka, c->d_ks, T_n, c->d_gcell);
   if (g_ka || brems)
     hipLaunchKernelGGL(k_tau_to_kappa, grid, block, 0, st, a, ngr, c->d_gcell, c->d_rho, c->d_ka, T_n, g_ka,
                        gT_n);
@@ -566,12 +590,11 @@ void reverse_step(rt_ctx* c, AdjArgs a, const void* I_n, const double* T_n, cons
 }  // namespace
 
 int adjoint_dir_groups(const rt_ctx* c) {
-  // enough (cell, direction group) threads to fill the GPU, about 16384 waves,
-  // in at most 4 groups (each group re-forms the face weights; 4 and 8 groups
-  // measured alike at 64^3, 32 slower)
-  const long long waves = (c->nc + 63) / 64;
+  // enough (segment, direction group) threads to fill the GPU, about 16384
+  // waves, in at most 16 groups (each group re-forms its faces' weights)
+  const long long waves = (c->nc / kAdjSeg + 63) / 64;
   long long g = (16384 + waves - 1) / waves;
-  if (g > 4) g = 4;
+  if (g > 16) g = 16;
   if (g > c->ns) g = c->ns;
   return (int)(g < 1 ? 1 : g);
 }

@@ -45,6 +45,28 @@ def test_adjoint_matches_oracle_gradient(case):
         assert err < 1e-10, (name, err)
 
 
+@pytest.mark.parametrize("n, bc", [((2, 3, 9), ("periodic", "periodic", "zero_incoming")),
+                                   ((1, 5, 3), ("outflow", "periodic", "outflow")),
+                                   ((9, 2, 5), ("zero_incoming", "periodic", "periodic"))])
+def test_adjoint_short_lines_match_oracle_gradient(n, bc):
+    """Lines shorter than a stencil (periodic lines of 2 and 3 cells wrap a face
+    onto itself; a clamped line of one cell is its own ghost on both sides) and
+    segments of the transport adjoint with a ragged end, FP64 against the
+    oracle's autograd."""
+    rng = np.random.default_rng(sum(n))
+    wl = W.adjoint_flat(n=n, generation=1, seed=sum(n))
+    wl["bc"] = bc
+    wl["kappa_s"] = rng.uniform(0.0, 0.8, n)
+    I0 = W.random_intensity(42, n, 3 + sum(n), 0.0, 0.4)
+    wts = rng.uniform(-1.0, 1.0, (42,) + n)
+    _say(f"adjoint short lines {n} {bc}")
+    gI, gk, gj = gpu_grad(wl, 2, I0, wts)
+    oI, ok, oj = oracle_grad(wl, 2, I0, wts)
+    for name, a, b in (("I", gI, oI), ("kappa_a", gk, ok), ("j", gj, oj)):
+        err = (a - b).abs().max().item() / max(b.abs().max().item(), 1e-300)
+        assert err < 1e-10, (name, err)
+
+
 def test_adjoint_fp32_matches_oracle_gradient():
     n = (6, 5, 7)
     rng = np.random.default_rng(5)
