@@ -77,29 +77,29 @@ __device__ Wts weights(double tau) {
 }
 
 // half of the limited slope and its partial derivatives (the active branch)
-template <int LIM>
-__device__ __forceinline__ double hslope(double p, double q, double& dp, double& dq) {
-  dp = dq = 0.0;
-  if (!(p * q > 0.0)) return 0.0;
+template <int LIM, typename T>
+__device__ __forceinline__ T hslope(T p, T q, T& dp, T& dq) {
+  dp = dq = T(0);
+  if (!(p * q > T(0))) return T(0);
   if (LIM == RT_LIM_MC) {
-    const double ap = fabs(p), aq = fabs(q), as = 0.25 * fabs(p + q);
+    const T ap = fabs(p), aq = fabs(q), as = T(0.25) * fabs(p + q);
     if (ap <= aq && ap <= as) {
-      dp = 1.0;
+      dp = T(1);
       return p;
     }
     if (aq <= as) {
-      dq = 1.0;
+      dq = T(1);
       return q;
     }
-    dp = dq = 0.25;
-    return 0.25 * (p + q);
+    dp = dq = T(0.25);
+    return T(0.25) * (p + q);
   }
   if (fabs(p) <= fabs(q)) {
-    dp = 0.5;
-    return 0.5 * p;
+    dp = T(0.5);
+    return T(0.5) * p;
   }
-  dq = 0.5;
-  return 0.5 * q;
+  dq = T(0.5);
+  return T(0.5) * q;
 }
 
 struct AdjArgs {
@@ -312,7 +312,7 @@ __device__ __forceinline__ int wrapp(int i, int n, bool periodic) {
 }
 
 template <typename S, int LIM, int L>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(S) == 4 ? 3 : 2)))
 k_tr_adj(AdjArgs a, int ax, int init, const S* __restrict__ If, const S* __restrict__ gIt, const S* add0,
          const S* add1, S* out, const double* __restrict__ dir, const double* __restrict__ rho,
          const double* __restrict__ ka, const double* __restrict__ ks, const double* __restrict__ Tc,
@@ -358,13 +358,13 @@ k_tr_adj(AdjArgs a, int ax, int init, const S* __restrict__ If, const S* __restr
   const int nfaces = per ? na : na + 1;
   bool fv[NF];
   S wP[NF], wQ[NF], wU[NF], wV[NF];
-  double dP[L + 1], dQ[L + 1], dU[L + 1], dV[L + 1];
+  S dP[L + 1], dQ[L + 1], dU[L + 1], dV[L + 1];
 #pragma unroll
   for (int q = 0; q < NF; ++q) {
     const int f = m0 - 1 + q;
     fv[q] = per || (f >= 0 && f < nfaces);
     wP[q] = wQ[q] = wU[q] = wV[q] = S(0);
-    if (q >= 1 && q <= L + 1) dP[q - 1] = dQ[q - 1] = dU[q - 1] = dV[q - 1] = 0.0;
+    if (q >= 1 && q <= L + 1) dP[q - 1] = dQ[q - 1] = dU[q - 1] = dV[q - 1] = S(0);
     if (!fv[q] || q > ncell + 2) continue;
     const long long cl = base + (long long)wrapp(f - 1, na, per) * sa;
     const long long cr = base + (long long)wrapp(f, na, per) * sa;
@@ -374,57 +374,60 @@ k_tr_adj(AdjArgs a, int ax, int init, const S* __restrict__ If, const S* __restr
     wU[q] = (S)w.U2;
     wV[q] = (S)w.V2;
     if (q >= 1 && q <= L + 1) {
-      dP[q - 1] = w.dP;
-      dQ[q - 1] = w.dQ;
-      dU[q - 1] = w.dU2;
-      dV[q - 1] = w.dV2;
+      dP[q - 1] = (S)w.dP;
+      dQ[q - 1] = (S)w.dQ;
+      dU[q - 1] = (S)w.dU2;
+      dV[q - 1] = (S)w.dV2;
     }
   }
   const bool owns_n = !per && last;  // face n, q = ncell + 1
   double tg[L + 1];
 #pragma unroll
   for (int q = 0; q <= L; ++q) tg[q] = 0.0;
-  const double hdx = a.inv_dx[ax] * a.h;
+  // the per-face arithmetic and the cell sums run in the storage type (FP32 in
+  // the FP32 form, as the forward transport does); the tau-gradients sum in FP64
+  const S hdx = (S)(a.inv_dx[ax] * a.h);
   for (int s = s_lo; s < s_hi; ++s) {
     const long long lb = (long long)s * a.nc + base;  // this direction's line
-    const double nu = dir[ax * a.ns + s];
-    const bool pos = nu > 0.0;
+    const S nu = (S)dir[ax * a.ns + s];
+    const bool pos = nu > S(0);
     // forward values at positions m0-3+j (zero for a zeroed ghost) and dL/dI~ at
     // m0-2+j (zero at ghosts: they are not updated)
-    double v[L + 6], gc[L + 4];
+    S v[L + 6], gc[L + 4];
 #pragma unroll
     for (int j = 0; j < L + 6; ++j) {
       const int p = m0 - 3 + j;
       const bool z = (p < 0 && zlo && pos) || (p >= na && zhi && !pos);
-      v[j] = (z || p > m0 + ncell + 2) ? 0.0 : (double)If[lb + po[j]];
+      v[j] = (z || p > m0 + ncell + 2) ? S(0) : If[lb + po[j]];
     }
 #pragma unroll
     for (int j = 0; j < L + 4; ++j) {
       const int p = m0 - 2 + j;
-      gc[j] = ((!per && (p < 0 || p >= na)) || p > m0 + ncell + 1) ? 0.0 : (double)gIt[lb + po[j + 1]];
+      gc[j] = ((!per && (p < 0 || p >= na)) || p > m0 + ncell + 1) ? S(0) : gIt[lb + po[j + 1]];
     }
-    double acc[L];
+    S acc[L];
 #pragma unroll
-    for (int i = 0; i < L; ++i) acc[i] = 0.0;
+    for (int i = 0; i < L; ++i) acc[i] = S(0);
 #pragma unroll
     for (int q = 0; q < NF; ++q) {
       if (!fv[q] || q > ncell + 2) continue;
       // face f = m0-1+q between positions f-1 and f (gc[q], gc[q+1]); F
       // contributes -h F/dx to I~(f-1) and +h F/dx to I~(f): dL/dF = gF
-      const double gF = (gc[q + 1] - gc[q]) * hdx;
-      if (gF == 0.0) continue;
-      const double v0 = v[q], v1 = v[q + 1], v2 = v[q + 2], v3 = v[q + 3];
-      const double cP = pos ? wP[q] : wQ[q], cQ = pos ? wQ[q] : wP[q];
-      const double cU = pos ? wU[q] : wV[q], cV = pos ? wV[q] : wU[q];
-      double a0, a1, b1, b2;
-      const double hL = hslope<LIM>(v1 - v0, v2 - v1, a0, a1);
-      const double hR = hslope<LIM>(v2 - v1, v3 - v2, b1, b2);
+      const S gF = (gc[q + 1] - gc[q]) * hdx;
+      if (gF == S(0)) continue;
+      const S v0 = v[q], v1 = v[q + 1], v2 = v[q + 2], v3 = v[q + 3];
+      const S cP = pos ? wP[q] : wQ[q], cQ = pos ? wQ[q] : wP[q];
+      const S cU = pos ? wU[q] : wV[q], cV = pos ? wV[q] : wU[q];
+      S a0, a1, b1, b2;
+      const S hL = hslope<LIM>(v1 - v0, v2 - v1, a0, a1);
+      const S hR = hslope<LIM>(v2 - v1, v3 - v2, b1, b2);
       // gF dF/d(positions f-2 .. f+1)
-      double g[4];
-      g[0] = gF * nu * (-cU * a0);
-      g[1] = gF * nu * (cP + cU * (a0 - a1) + cV * b1);
-      g[2] = gF * nu * (cQ + cU * a1 - cV * (b1 - b2));
-      g[3] = gF * nu * (-cV * b2);
+      const S gn = gF * nu;
+      S g[4];
+      g[0] = gn * (-cU * a0);
+      g[1] = gn * (cP + cU * (a0 - a1) + cV * b1);
+      g[2] = gn * (cQ + cU * a1 - cV * (b1 - b2));
+      g[3] = gn * (-cV * b2);
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
         const int i = q - 3 + k;  // position m0 + i
@@ -436,16 +439,16 @@ k_tr_adj(AdjArgs a, int ax, int init, const S* __restrict__ If, const S* __restr
         }
       }
       if ((q >= 1 && q <= ncell) || (owns_n && q == ncell + 1)) {
-        const double dcP = pos ? dP[q - 1] : dQ[q - 1], dcQ = pos ? dQ[q - 1] : dP[q - 1];
-        const double dcU = pos ? dU[q - 1] : dV[q - 1], dcV = pos ? dV[q - 1] : dU[q - 1];
-        tg[q - 1] += gF * nu * (dcP * v1 + dcQ * v2 + dcU * hL - dcV * hR);
+        const S dcP = pos ? dP[q - 1] : dQ[q - 1], dcQ = pos ? dQ[q - 1] : dP[q - 1];
+        const S dcU = pos ? dU[q - 1] : dV[q - 1], dcV = pos ? dV[q - 1] : dU[q - 1];
+        tg[q - 1] += (double)(gn * (dcP * v1 + dcQ * v2 + dcU * hL - dcV * hR));
       }
     }
 #pragma unroll
     for (int i = 0; i < L; ++i) {
       if (i >= ncell) break;
       const long long o = lb + (long long)(m0 + i) * sa;
-      double x = acc[i];
+      double x = (double)acc[i];
       if (init) {
         if (add0) x += (double)add0[o];
         if (add1) x += (double)add1[o];
