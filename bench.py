@@ -240,6 +240,26 @@ def roofline_block(wkey, r):
     return blk
 
 
+def copy_ceiling(torch):
+    """Measured device-copy bandwidth: a plain 1 GiB device-to-device copy,
+    5 repeats timed with HIP events after one warm-up (bytes read + written
+    over the mean time)."""
+    src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(5):
+        dst.copy_(src)
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / 5
+    del src, dst
+    torch.cuda.empty_cache()
+    return {"GBs": 2 * (1 << 30) / (ms / 1e3) / 1e9, "ms": ms, "bytes_moved": 2 * (1 << 30),
+            "frac_of_peak": 2 * (1 << 30) / (ms / 1e3) / 1e9 / HBM_PEAK_GBS}
+
+
 def cpu_baseline(torch):
     """The FP64 oracle, as it stands, on a bounded sample of the same workload:
     a periodic 64^3 sub-box x 162 directions, two steps (about 10-30 s)."""
@@ -667,7 +687,7 @@ def main():
         out["torus_ks_mapr"] = run_only("mapr", min(args.steps, 5), 1, torch, P, W)
     if not args.no_big_torus:
         try:
-            out["torus_ks_384x192x128_g3"] = run_only("bigtorus", 5, 1, torch, P, W)
+            out["torus_ks_384x192x128_g3"] = run_only("bigtorus", args.steps, 1, torch, P, W)
         except Exception as e:  # reported in the line, the headline stands
             out["torus_ks_384x192x128_g3"] = {"error": f"{type(e).__name__}: {e}"}
     if not args.no_adjoint:
@@ -680,6 +700,7 @@ def main():
     # materialisation pass instead)
     print("bench: rt_moments 128^3 x 162", file=sys.stderr, flush=True)
     out["moments"] = [run_moments(wl, prec, 10, 2, torch, P) for prec in forms]
+    out["device_copy_ceiling"] = copy_ceiling(torch)
     acc = accuracy_record()
     if acc is not None:
         out["accuracy_fp32_vs_oracle"] = acc
