@@ -139,6 +139,23 @@ __device__ __forceinline__ void cell_opac_T(const AdjArgs& a, const double* rho,
   if (!(r >= a.rho_floor)) aa = as = 0.0;
 }
 
+// out[s][c] = a * in[s][c] + b * w[s] for every direction of cell c, in batches
+// of 8 directions whose loads are all issued before their stores (out may be
+// in: each element is read before it is written)
+template <typename S>
+__device__ __forceinline__ void scale_dirs(S* out, const S* in, long long nc, int ns, long long c, double a,
+                                           double b, const double* __restrict__ w) {
+  constexpr int B = 8;
+  for (int s0 = 0; s0 < ns; s0 += B) {
+    double v[B];
+#pragma unroll
+    for (int u = 0; u < B; ++u) v[u] = (double)in[(long long)min(s0 + u, ns - 1) * nc + c];
+#pragma unroll
+    for (int u = 0; u < B; ++u)
+      if (s0 + u < ns) out[(long long)(s0 + u) * nc + c] = (S)(a * v[u] + b * w[s0 + u]);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // interaction adjoint of the bremsstrahlung model (Method 2) at rest, one
 // thread per cell.  Forward (h = this stage's length, Ts = T_start, Tc = T_coef):
@@ -165,7 +182,7 @@ k_src_adj_brems(AdjArgs a, const S* __restrict__ It, const S* gI, S* gIt, const 
   const double gT = gTo ? gTo[c] : 0.0;
   const double h = a.h, k4 = 1.0 / (4.0 * kPi);
   auto passthrough = [&]() {
-    for (int s = 0; s < a.ns; ++s) gIt[(long long)s * a.nc + c] = gI[(long long)s * a.nc + c];
+    scale_dirs(gIt, gI, a.nc, a.ns, c, 1.0, 0.0, w);
     gTs[c] += gT;
   };
   if (!(r >= a.rho_floor)) {
@@ -176,6 +193,7 @@ k_src_adj_brems(AdjArgs a, const S* __restrict__ It, const S* gI, S* gIt, const 
   const double aa = aam * m, as = a.C_s * r, ab = aa + as;
   const double al = 1.0 / (1.0 + ab * h);
   double Em = 0.0, G = 0.0, GI = 0.0;
+#pragma unroll 8
   for (int s = 0; s < a.ns; ++s) {
     const double x = (double)It[(long long)s * a.nc + c], g = (double)gI[(long long)s * a.nc + c];
     Em += w[s] * x;
@@ -226,10 +244,7 @@ k_src_adj_brems(AdjArgs a, const S* __restrict__ It, const S* gI, S* gIt, const 
   gTs[c] += g_ts;
   gTc[c] += g_aa * (-3.5 * aa / tc);
   if (gka) gka[c] += g_aa * aam + g_N * Nm;
-  for (int s = 0; s < a.ns; ++s) {
-    const long long i = (long long)s * a.nc + c;
-    gIt[i] = (S)(al * (double)gI[i] + g_Em * w[s]);
-  }
+  scale_dirs(gIt, gI, a.nc, a.ns, c, al, g_Em, w);
 }
 
 // ---------------------------------------------------------------------------
@@ -247,7 +262,7 @@ k_src_adj(AdjArgs a, const S* __restrict__ It, const S* gI, S* gIt, const double
   double r, aa, as;
   cell_opac(a, rho, ka, ks, c, r, aa, as);
   if (!(r >= a.rho_floor)) {
-    for (int s = 0; s < a.ns; ++s) gIt[(long long)s * a.nc + c] = gI[(long long)s * a.nc + c];
+    scale_dirs(gIt, gI, a.nc, a.ns, c, 1.0, 0.0, w);
     return;
   }
   const double h = a.h, ab = aa + as;
@@ -257,6 +272,7 @@ k_src_adj(AdjArgs a, const S* __restrict__ It, const S* gI, S* gIt, const double
   const double q = 1.0 - A2 * as;
   const double Se = 4.0 * kPi * (jv ? jv[c] : 0.0);
   double Em = 0.0, G = 0.0, GI = 0.0;
+#pragma unroll 8
   for (int s = 0; s < a.ns; ++s) {
     const double x = (double)It[(long long)s * a.nc + c], g = (double)gI[(long long)s * a.nc + c];
     Em += w[s] * x;
@@ -267,10 +283,7 @@ k_src_adj(AdjArgs a, const S* __restrict__ It, const S* gI, S* gIt, const double
   const double Q = Se + as * Ep;
   // dL/dI~_s = c g_s + (G d alpha^s c / q) w_s
   const double kw = G * dd * as * cc / q;
-  for (int s = 0; s < a.ns; ++s) {
-    const long long i = (long long)s * a.nc + c;
-    gIt[i] = (S)(cc * (double)gI[i] + kw * w[s]);
-  }
+  scale_dirs(gIt, gI, a.nc, a.ns, c, cc, kw, w);
   // parameter derivatives through alpha = rho (kappa_a + kappa_s) and S = 4 pi j
   const double dc = -h * cc * cc;
   const double ddd = h * dc / (4.0 * kPi);
