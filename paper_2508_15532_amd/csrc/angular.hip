@@ -276,6 +276,19 @@ k_mapr_flux(long long nc, int n3, int ns, const S* __restrict__ I, const S* __re
   const S* w = pq + s * KS_ROW * 4;
   const S Is = I[(long long)s * nc + c];
   const S gs0 = G[2LL * s * nc + c], gs1 = G[(2LL * s + 1) * nc + c];
+  // the upwind neighbours' intensities and slopes: every load is issued before
+  // the first is used (the slot flags only decide which loads are needed)
+  S Iu[KS_DEG], Gu0[KS_DEG], Gu1[KS_DEG];
+#pragma unroll
+  for (int j = 1; j <= KS_DEG; ++j) {
+    Iu[j - 1] = Gu0[j - 1] = Gu1[j - 1] = S(0);
+    if (!((f >> j) & 1u)) {
+      const long long u = o[j];
+      Iu[j - 1] = I[u * nc + c];
+      Gu0[j - 1] = G[2 * u * nc + c];
+      Gu1[j - 1] = G[(2 * u + 1) * nc + c];
+    }
+  }
   S acc = 0;
 #pragma unroll
   for (int j = 1; j <= KS_DEG; ++j) {
@@ -284,10 +297,8 @@ k_mapr_flux(long long nc, int n3, int ns, const S* __restrict__ I, const S* __re
       r = Is + gs0 * w[4 * j] + gs1 * w[4 * j + 1];
       if (r < S(0)) r = Is;
     } else {
-      const long long u = o[j];
-      const S Iu = I[u * nc + c];
-      r = Iu + G[2 * u * nc + c] * w[4 * j + 2] + G[(2 * u + 1) * nc + c] * w[4 * j + 3];
-      if (r < S(0)) r = Iu;
+      r = Iu[j - 1] + Gu0[j - 1] * w[4 * j + 2] + Gu1[j - 1] * w[4 * j + 3];
+      if (r < S(0)) r = Iu[j - 1];
     }
     acc += a[j] * r;
   }
