@@ -1094,9 +1094,20 @@ hipError_t launch_stage(rt_ctx* c, const StageArgs& a, const StagePtrs& p, bool 
   if (c->fp32 && mv)
     return mc ? launch_tiled<float, float, 2, RT_LIM_MC, true>(c, a, p, stage2, st, may_alloc)
               : launch_tiled<float, float, 2, RT_LIM_MINMOD, true>(c, a, p, stage2, st, may_alloc);
-  if (c->fp32)
+  if (c->fp32) {
+    // columns of 4 cells, or of 2 when columns of 4 leave fewer than two tiles
+    // per compute unit (small grids: the same per-cell arithmetic, so the same
+    // results, on twice as many workgroups)
+    int cus = 256, dev = 0;
+    if (hipGetDevice(&dev) == hipSuccess)
+      (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    const long long tiles4 = (long long)((c->n[2] + TX - 1) / TX) * ((c->n[1] + 7) / 8) * ((c->n[0] + 3) / 4);
+    if (tiles4 < 2LL * cus && c->n[0] > 2)
+      return mc ? launch_tiled<float, float, 2, RT_LIM_MC, false>(c, a, p, stage2, st, may_alloc)
+                : launch_tiled<float, float, 2, RT_LIM_MINMOD, false>(c, a, p, stage2, st, may_alloc);
     return mc ? launch_tiled<float, float, 4, RT_LIM_MC, false>(c, a, p, stage2, st, may_alloc)
               : launch_tiled<float, float, 4, RT_LIM_MINMOD, false>(c, a, p, stage2, st, may_alloc);
+  }
   if (mv)
     return mc ? launch_tiled<double, double, 1, RT_LIM_MC, true>(c, a, p, stage2, st, may_alloc)
               : launch_tiled<double, double, 1, RT_LIM_MINMOD, true>(c, a, p, stage2, st, may_alloc);
