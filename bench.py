@@ -182,15 +182,23 @@ KERNEL_SOURCES = {
 }
 
 
+def _code_only(text):
+    """Source text without comments and blank lines (a comment edit leaves the
+    compiled kernel unchanged)."""
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    lines = (re.sub(r"//.*$", "", ln).rstrip() for ln in text.split("\n"))
+    return "\n".join(ln for ln in lines if ln.strip())
+
+
 def sources_sha256(names=None):
-    """Hash of the named library sources (default: every kernel and host
-    source), in sorted order."""
+    """Hash of the code (comments and blank lines removed) of the named library
+    sources (default: every kernel and host source), in sorted order."""
     h = hashlib.sha256()
     if names is None:
         names = [n for n in os.listdir(CSRC) if n.endswith((".hip", ".cpp", ".hpp"))]
     for name in sorted(set(names)):
         h.update(name.encode())
-        h.update(open(os.path.join(CSRC, name), "rb").read())
+        h.update(_code_only(open(os.path.join(CSRC, name), encoding="utf-8").read()).encode())
     return h.hexdigest()
 
 

@@ -1,7 +1,9 @@
-// Hand-written adjoint of one predictor-corrector step for a fluid at rest
-// with a fixed emissivity (temperature-independent opacities): gradients with
-// respect to the intensity of the step start, the per-cell absorption opacity
-// kappa_a and the emissivity j.
+// Hand-written adjoint of one predictor-corrector step for a fluid at rest in
+// flat space: with a fixed emissivity (temperature-independent opacities),
+// gradients with respect to the intensity of the step start, the per-cell
+// absorption opacity kappa_a and the emissivity j; with the bremsstrahlung
+// model (Method 2), with respect to the intensity and temperature of the step
+// start and the per-cell opacity factor, through the temperature solve.
 //
 // Forward (per stage, h = dt/2 then dt; tau uses the full dt in both stages):
 //   I~ = I_base - h D(I_flux),  D = sum_a (F(l+1/2) - F(l-1/2)) / dx_a,
@@ -10,11 +12,12 @@
 //   I_out = c I~ + d Q,  c = 1/(1 + alpha h),  d = h c/(4 pi),
 //   Q = S + alpha^s E+,  E+ = (c E- + A2 S)/q,  E- = sum_s w_s I~_s,
 //   A2 = d sum_s w_s,  q = 1 - A2 alpha^s,  S = 4 pi j,  alpha = rho (kappa_a + kappa_s).
-// Reverse: the interaction adjoint per cell, then the transport adjoint in
-// gather form (each cell collects the flux-derivative contributions of the
-// faces whose stencils contain it), then the tau-gradients of the faces are
-// reduced onto the cells' opacities.  No floating-point atomics: every sum has
-// one writer and a fixed order.
+// Reverse: the interaction adjoint per cell, then the transport adjoint (each
+// cell collects the flux-derivative contributions of the faces whose stencils
+// contain it; a thread forms the faces of a short segment of cells once and
+// adds their contributions to its cells), then the tau-gradients of the faces
+// are reduced onto the cells' opacities.  No floating-point atomics: every sum
+// has one writer and a fixed order.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
