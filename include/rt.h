@@ -193,7 +193,11 @@ rt_status rt_set_opacities(rt_ctx* ctx, const rt_opacity_desc* desc, hipStream_t
    While bins are set, rt_step and rt_step_noalloc take I as [ng][Ns][Nc] (bin
    major) and return R_out and G_out summed over the bins; a later
    rt_set_opacities that leaves this configuration makes rt_step return
-   RT_E_STATE.  The adjoints do not support bins (RT_E_ARG). */
+   RT_E_STATE.  The adjoints do not support bins (RT_E_ARG).  The call
+   reallocates the step scratch after synchronising `stream` (work enqueued on
+   other streams must be complete); if an allocation fails (RT_E_NOMEM) the
+   context is left gray and without its scratch, and rt_step returns
+   RT_E_STATE until a later rt_set_groups succeeds. */
 #define RT_MAX_GROUPS 64
 rt_status rt_set_groups(rt_ctx* ctx, int ng, const double* nu_edges_host, const double* kappa_a_groups,
                         hipStream_t stream);

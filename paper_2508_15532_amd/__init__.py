@@ -144,8 +144,10 @@ class RTContext:
             N.check(self._lib.rt_set_groups(self._ctx, 0, None, None, _stream()))
             self.ng = 0
             return
-        e = np.ascontiguousarray(np.asarray(edges, dtype=np.float64))
+        e = np.ascontiguousarray(np.asarray(edges, dtype=np.float64).reshape(-1))
         ng = e.size - 1
+        if ng < 1:
+            raise ValueError("edges needs at least two values (one bin); edges=None means gray")
         ka = _ptr(kappa_a_groups, "kappa_a_groups", torch.float64, ng * self.nc)
         N.check(self._lib.rt_set_groups(self._ctx, int(ng), e.ctypes.data_as(C.c_void_p), ka, _stream()))
         self.ng = ng

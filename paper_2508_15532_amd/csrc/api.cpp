@@ -452,7 +452,11 @@ rt_status step_impl(rt_ctx* c, const StepScratch& ws, bool may_alloc, void* I, d
   auto run = [&](int kind, auto&& launch) -> hipError_t {
     return may_alloc ? timed(c, kind, stream, launch) : launch();
   };
-  if (c->ng && (!ws.Emg || !ws.Itil || !ws.mapA || !ws.mapB || !ws.Tstar || !c->d_ka_g))
+  // (a failed reconfiguration, e.g. an allocation in rt_set_groups, can leave
+  // the context without its step scratch: refuse rather than launch on NULL)
+  if (!ws.Itil || !ws.mapA || !ws.mapB || !ws.Tstar || (c->curved && !ws.angD) || (c->mapr && !ws.mp_grad))
+    return fail(RT_E_STATE, "rt_step: the step scratch is not allocated");
+  if (c->ng && (!ws.Emg || !c->d_ka_g))
     return fail(RT_E_STATE, "rt_step: the frequency-bin scratch is not allocated");
   if (c->ng) {
     // frequency bins (at rest, flat): each stage transports every bin with its

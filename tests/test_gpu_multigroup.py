@@ -125,6 +125,8 @@ def test_bins_and_configuration_errors():
         with pytest.raises(RTError) as e:
             ctx.set_groups(edges, kag)
         assert e.value.status == -1
+    with pytest.raises(ValueError):
+        ctx.set_groups((0.0,), kag)  # one edge is no bin
     ctx.set_groups(wl["group_edges"], kag)
     # a later change to a model the bins do not support is refused at the step
     rho = torch.as_tensor(wl["rho"], dtype=F64, device=dev).reshape(-1).contiguous()
