@@ -73,6 +73,11 @@ __device__ __forceinline__ T half_slope(T p, T q) {
   return T(0.5) * med0(p, q);
 }
 
+// a read-only device array in the constant address space (loads at uniform
+// addresses become scalar loads)
+template <typename T>
+using CPtr = const __attribute__((address_space(4))) T*;
+
 // One direction's plane of nc cells as a buffer resource: loads and stores
 // take a uniform base and an unsigned 32-bit byte offset per lane, so the
 // direction loop carries no 64-bit address arithmetic.
@@ -80,6 +85,9 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const void* base, u
   // stride 0, raw dword addressing (the data-format word of the gfx9 family)
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
 }
+// a byte offset at or past the end of any plane (a plane holds fewer than
+// 2^29 cells of at most 8 bytes): buffer stores there are dropped by the range check
+constexpr unsigned kDropOffset = 0xFFFFFFF8u;
 template <typename T>
 __device__ __forceinline__ T bload(__amdgpu_buffer_rsrc_t r, unsigned off) {
   static_assert(sizeof(T) == 4 || sizeof(T) == 8, "dword or dwordx2");
@@ -569,7 +577,12 @@ k_stage(StageArgs a, StagePtrs p) {
   const F h = (F)a.h;
   const F idx0 = (F)a.inv_dx[0], idx1 = (F)a.inv_dx[1], idx2 = (F)a.inv_dx[2];
   const int ns = a.ns;
-  const F* __restrict__ dirF = (const F*)p.dirF_v;
+  // per-direction constants through the constant address space: uniform
+  // scalar loads, which wait on the scalar counter only (a vector load here
+  // would wait behind the plane stores and prefetches of the direction loop)
+  const CPtr<F> dirF = (CPtr<F>)p.dirF_v;
+  const CPtr<double> wdir = (CPtr<double>)p.w;
+  const CPtr<double> dirD = (CPtr<double>)p.dirD;
   const S* angD = (const S*)p.angD_v;
 
   // ---- prefetch of direction 0
@@ -595,6 +608,11 @@ k_stage(StageArgs a, StagePtrs p) {
     }
   };
   prefetch(0);
+  // Direction 0's loads complete before the loop: then the only loads pending
+  // at the top of an iteration are the prefetch of the previous one, issued
+  // before its stores, and the compiler's wait for them can leave those stores
+  // in flight (s_waitcnt vmcnt(0), other counters untouched)
+  if constexpr (!MOVING) __builtin_amdgcn_s_waitcnt(0x0F70);
 
   // a thread with no zero-incoming ghost among its slots skips the checks
   bool anyghost = false;
@@ -731,7 +749,7 @@ k_stage(StageArgs a, StagePtrs p) {
     }
 
     // 3. divergence, update, interaction sums
-    const double ws = p.w[s];
+    const double ws = wdir[s];
     const double hw4 = a.h / (4.0 * kPi) * ws;
     const F cz = NUOUT ? h * nz * idx0 : h * idx0, cy = NUOUT ? h * ny * idx1 : h * idx1,
             cx = NUOUT ? h * nx * idx2 : h * idx2;
@@ -748,11 +766,19 @@ k_stage(StageArgs a, StagePtrs p) {
       } else {
         It = base[k] - (dz * cz + dy * cy + dx * cx);
       }
-      if (valid[k]) st(Iout + (long long)s * nc, woff[k + 2], wcell[k + 2], (S)It);
+      if constexpr (MOVING) {
+        if (valid[k]) st(Iout + (long long)s * nc, woff[k + 2], wcell[k + 2], (S)It);
+      } else {
+        // every lane stores: a cell outside the grid gets an offset past the
+        // plane, which the buffer's range check drops.  Unconditional stores
+        // keep the count of outstanding vector operations known, so the wait
+        // for the next direction's loads need not wait for these stores too.
+        st(Iout + (long long)s * nc, valid[k] ? woff[k + 2] : kDropOffset, 0, (S)It);
+      }
       // ---- interaction sums (FP64)
       const double Itd = (double)(S)It;
       if (MOVING) {
-        const double nb = u0[k] - (u1[k] * p.dirD[s] + u2[k] * p.dirD[ns + s] + u3[k] * p.dirD[2 * ns + s]);
+        const double nb = u0[k] - (u1[k] * dirD[s] + u2[k] * dirD[ns + s] + u3[k] * dirD[2 * ns + s]);
         // with Ib = I~ nb^4, dOb = w / nb^2 and den = n^0 + nb abar h:
         //   Ib dOb = w I~ nb^2,  n^0 Ib dOb / den,  nb h dOb / (4 pi den) = h w / (4 pi nb den)
         // (one division: q = 1 / (nb den))
