@@ -612,7 +612,7 @@ k_stage(StageArgs a, StagePtrs p) {
   // at the top of an iteration are the prefetch of the previous one, issued
   // before its stores, and the compiler's wait for them can leave those stores
   // in flight (s_waitcnt vmcnt(0), other counters untouched)
-  if constexpr (!MOVING) __builtin_amdgcn_s_waitcnt(0x0F70);
+  __builtin_amdgcn_s_waitcnt(0x0F70);
 
   // a thread with no zero-incoming ghost among its slots skips the checks
   bool anyghost = false;
@@ -766,15 +766,11 @@ k_stage(StageArgs a, StagePtrs p) {
       } else {
         It = base[k] - (dz * cz + dy * cy + dx * cx);
       }
-      if constexpr (MOVING) {
-        if (valid[k]) st(Iout + (long long)s * nc, woff[k + 2], wcell[k + 2], (S)It);
-      } else {
-        // every lane stores: a cell outside the grid gets an offset past the
-        // plane, which the buffer's range check drops.  Unconditional stores
-        // keep the count of outstanding vector operations known, so the wait
-        // for the next direction's loads need not wait for these stores too.
-        st(Iout + (long long)s * nc, valid[k] ? woff[k + 2] : kDropOffset, 0, (S)It);
-      }
+      // every lane stores: a cell outside the grid gets an offset past the
+      // plane, which the buffer's range check drops.  Unconditional stores
+      // keep the count of outstanding vector operations known, so the wait
+      // for the next direction's loads need not wait for these stores too.
+      bstore<S>(plane_rsrc(Iout + (long long)s * nc, pbytes), valid[k] ? woff[k + 2] : kDropOffset, (S)It);
       // ---- interaction sums (FP64)
       const double Itd = (double)(S)It;
       if (MOVING) {
