@@ -30,14 +30,6 @@ namespace {
 
 constexpr double kPi = 3.14159265358979323846;
 
-__device__ __forceinline__ int wrapc(int i, int n, bool periodic) {
-  if (periodic) {
-    i %= n;
-    return i < 0 ? i + n : i;
-  }
-  return i < 0 ? 0 : (i >= n ? n - 1 : i);
-}
-
 // flux weights of a face and their derivatives with respect to tau
 struct Wts {
   double P, Q, U2, V2;     // F = nu (P IcL + Q IcR + U2 hL - V2 hR)

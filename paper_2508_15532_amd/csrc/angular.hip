@@ -277,13 +277,18 @@ k_mapr_flux(long long nc, int n3, int ns, const S* __restrict__ I, const S* __re
   const S Is = I[(long long)s * nc + c];
   const S gs0 = G[2LL * s * nc + c], gs1 = G[(2LL * s + 1) * nc + c];
   // the upwind neighbours' intensities and slopes: every load is issued before
-  // the first is used (the slot flags only decide which loads are needed)
+  // the first is used (the slot flags only decide which loads are needed); the
+  // neighbour numbers are read first, all at once, rather than one per slot
+  // behind each slot's flag
+  int on[KS_DEG];
+#pragma unroll
+  for (int j = 1; j <= KS_DEG; ++j) on[j - 1] = o[j];
   S Iu[KS_DEG], Gu0[KS_DEG], Gu1[KS_DEG];
 #pragma unroll
   for (int j = 1; j <= KS_DEG; ++j) {
     Iu[j - 1] = Gu0[j - 1] = Gu1[j - 1] = S(0);
     if (!((f >> j) & 1u)) {
-      const long long u = o[j];
+      const long long u = on[j - 1];
       Iu[j - 1] = I[u * nc + c];
       Gu0[j - 1] = G[2 * u * nc + c];
       Gu1[j - 1] = G[(2 * u + 1) * nc + c];

@@ -142,6 +142,7 @@ k_mg_solve(MgArgs a, const double* __restrict__ Emg, const double* __restrict__ 
            const double* __restrict__ kag, const double* __restrict__ ks, const double* T_start,
            const double* T_guess, double* T_out, double* __restrict__ map,
            unsigned long long* __restrict__ fail) {
+  constexpr int kUnroll = NGR > 0 ? NGR : 1;  // the bin loops: unrolled when bounded
   const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   const long long nc = a.nc;
   if (c >= nc) return;
@@ -157,7 +158,7 @@ k_mg_solve(MgArgs a, const double* __restrict__ Emg, const double* __restrict__ 
   double excess = 0.0;
   double Kr[NGR > 0 ? NGR : 1];
   if (live) {
-#pragma unroll
+#pragma unroll kUnroll
     for (int g = 0; g < (NGR > 0 ? NGR : a.ng); ++g) {
       if (NGR > 0 && g >= a.ng) break;
       const double aa = r * kag[g * nc + c], den = 1.0 + (aa + as) * a.h;
@@ -170,7 +171,7 @@ k_mg_solve(MgArgs a, const double* __restrict__ Emg, const double* __restrict__ 
     const double iT = 1.0 / T, T3 = T * T * T;
     double sD = 0.0, sdD = 0.0;
     EdgeVal ea = edge_val(a.nu[0] * iT, lo2, hi2);
-#pragma unroll
+#pragma unroll kUnroll
     for (int g = 0; g < (NGR > 0 ? NGR : a.ng); ++g) {
       if (NGR > 0 && g >= a.ng) break;
       const EdgeVal eb = edge_val(a.nu[g + 1] * iT, lo2, hi2);

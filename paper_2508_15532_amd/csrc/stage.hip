@@ -434,17 +434,14 @@ k_stage(StageArgs a, StagePtrs p) {
 #pragma unroll
   for (int k = 0; k < TZ; ++k) yoff[k] = (unsigned)ycell[k] * (unsigned)sizeof(S);
   const unsigned xoff = (unsigned)xcell * (unsigned)sizeof(S);
-  // At rest the loads and stores go through buffer resources with these
-  // offsets; the moving kernels, which are register bound, index with the cell
-  // numbers (fewer registers live across their loop).
+  // Stores go through buffer resources with these offsets, and so do the
+  // loads at rest; the moving kernels' loads, which would need a resource per
+  // plane (too many scalar registers in these register-bound kernels), index
+  // with the cell numbers.
   const unsigned pbytes = (unsigned)nc * (unsigned)sizeof(S);
   auto ld = [&](const S* base, unsigned off, int cell) -> S {
     if constexpr (MOVING) return base[cell];
     else return bload<S>(plane_rsrc(base, pbytes), off);
-  };
-  auto st = [&](S* base, unsigned off, int cell, S v) {
-    if constexpr (MOVING) base[cell] = v;
-    else bstore<S>(plane_rsrc(base, pbytes), off, v);
   };
 
   // ---- coefficients of the faces this thread computes (direction independent)
