@@ -395,23 +395,55 @@ k_tr_adj(AdjArgs a, int ax, int init, const S* __restrict__ If, const S* __restr
   // the per-face arithmetic and the cell sums run in the storage type (FP32 in
   // the FP32 form, as the forward transport does); the tau-gradients sum in FP64
   const S hdx = (S)(a.inv_dx[ax] * a.h);
+  // A direction's loads: the forward values at positions m0-3+j, dL/dI~ at
+  // m0-2+j and what each cell's result adds to (add0 + add1 on the first axis,
+  // else out).  They are issued one direction ahead, and unconditionally
+  // (every position is a valid cell; ghosts and the cells past a short
+  // segment are zeroed or dropped after the load; absent addends read If and
+  // are not used), as are the stores (a cell past the segment's end repeats
+  // the last cell's store), so that the wait for the next direction's loads
+  // does not also wait for this direction's stores.
+  const S* src0 = init ? (add0 ? add0 : If) : (const S*)out;
+  const S* src1 = (init && add1) ? add1 : If;
+  const bool use0 = !init || add0 != nullptr, use1 = init && add1 != nullptr;
+  struct DirLoads {
+    S v[L + 6], gc[L + 4], b0[L], b1[L];
+  };
+  auto issue = [&](int s, DirLoads& d) {
+    const long long lb = (long long)s * a.nc + base;
+#pragma unroll
+    for (int j = 0; j < L + 6; ++j) d.v[j] = If[lb + po[j]];
+#pragma unroll
+    for (int j = 0; j < L + 4; ++j) d.gc[j] = gIt[lb + po[j + 1]];
+#pragma unroll
+    for (int i = 0; i < L; ++i) {
+      const long long o = lb + (long long)(m0 + min(i, ncell - 1)) * sa;
+      d.b0[i] = src0[o];
+      d.b1[i] = src1[o];
+    }
+  };
+  DirLoads cur;
+  if (s_lo < s_hi) issue(s_lo, cur);
+  __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): the first direction's loads
   for (int s = s_lo; s < s_hi; ++s) {
+    DirLoads nxt;
+    issue(min(s + 1, s_hi - 1), nxt);
     const long long lb = (long long)s * a.nc + base;  // this direction's line
     const S nu = (S)dir[ax * a.ns + s];
     const bool pos = nu > S(0);
-    // forward values at positions m0-3+j (zero for a zeroed ghost) and dL/dI~ at
-    // m0-2+j (zero at ghosts: they are not updated)
+    // forward values (zero for a zeroed ghost) and dL/dI~ (zero at ghosts:
+    // they are not updated)
     S v[L + 6], gc[L + 4];
 #pragma unroll
     for (int j = 0; j < L + 6; ++j) {
       const int p = m0 - 3 + j;
       const bool z = (p < 0 && zlo && pos) || (p >= na && zhi && !pos);
-      v[j] = (z || p > m0 + ncell + 2) ? S(0) : If[lb + po[j]];
+      v[j] = (z || p > m0 + ncell + 2) ? S(0) : cur.v[j];
     }
 #pragma unroll
     for (int j = 0; j < L + 4; ++j) {
       const int p = m0 - 2 + j;
-      gc[j] = ((!per && (p < 0 || p >= na)) || p > m0 + ncell + 1) ? S(0) : gIt[lb + po[j + 1]];
+      gc[j] = ((!per && (p < 0 || p >= na)) || p > m0 + ncell + 1) ? S(0) : cur.gc[j];
     }
     S acc[L];
 #pragma unroll
@@ -452,18 +484,30 @@ k_tr_adj(AdjArgs a, int ax, int init, const S* __restrict__ If, const S* __restr
         tg[q - 1] += (double)(gn * (dcP * v1 + dcQ * v2 + dcU * hL - dcV * hR));
       }
     }
+    S xv[L];
 #pragma unroll
     for (int i = 0; i < L; ++i) {
-      if (i >= ncell) break;
-      const long long o = lb + (long long)(m0 + i) * sa;
       double x = (double)acc[i];
-      if (init) {
-        if (add0) x += (double)add0[o];
-        if (add1) x += (double)add1[o];
-      } else {
-        x += (double)out[o];
-      }
-      out[o] = (S)x;
+      if (use0) x += (double)cur.b0[i];
+      if (use1) x += (double)cur.b1[i];
+      xv[i] = (S)x;
+    }
+#pragma unroll
+    for (int i = 0; i < L; ++i) {
+      S val = xv[0];
+#pragma unroll
+      for (int k = 1; k <= i; ++k)
+        if (k < ncell) val = xv[k];
+      out[lb + (long long)(m0 + min(i, ncell - 1)) * sa] = val;
+    }
+#pragma unroll
+    for (int j = 0; j < L + 6; ++j) cur.v[j] = nxt.v[j];
+#pragma unroll
+    for (int j = 0; j < L + 4; ++j) cur.gc[j] = nxt.gc[j];
+#pragma unroll
+    for (int i = 0; i < L; ++i) {
+      cur.b0[i] = nxt.b0[i];
+      cur.b1[i] = nxt.b1[i];
     }
   }
   // this group's per-face tau gradients of this axis: the lower face of each
