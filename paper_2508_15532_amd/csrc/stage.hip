@@ -895,17 +895,25 @@ k_materialize(long long nc, int ns, double h, const double* __restrict__ map, S*
   double R[10];
   for (int m = 0; m < 10; ++m) R[m] = 0.0;
   double g[4] = {0.0, 0.0, 0.0, 0.0};
-  // batches of B directions: all loads of a batch are issued before its stores
+  // batches of B directions, the next batch's loads issued before this
+  // batch's arithmetic (the batches are disjoint directions).  Stores go
+  // through buffer resources and every lane stores (a cell that keeps I~
+  // stores at an offset the range check drops), so waiting for the next
+  // batch's loads does not wait for this batch's stores.
   constexpr int B = 8;
-  for (int s0 = 0; s0 < ns; s0 += B) {
-    S v[B];
+  const unsigned pbytes = (unsigned)nc * (unsigned)sizeof(S);
+  const unsigned soff = (use || zero) ? (unsigned)c * (unsigned)sizeof(S) : kDropOffset;
+  S v[B];
 #pragma unroll
-    for (int u = 0; u < B; ++u) v[u] = I[(long long)min(s0 + u, ns - 1) * nc + c];
+  for (int u = 0; u < B; ++u) v[u] = I[(long long)min(u, ns - 1) * nc + c];
+  for (int s0 = 0; s0 < ns; s0 += B) {
+    S vn[B];
+#pragma unroll
+    for (int u = 0; u < B; ++u) vn[u] = I[(long long)min(s0 + B + u, ns - 1) * nc + c];
 #pragma unroll
     for (int u = 0; u < B; ++u) {
       const int s = s0 + u;
       if (s >= ns) break;
-      S* q = I + (long long)s * nc + c;
       const double It = (double)v[u];
       double Io = It;
       if (use) {
@@ -914,11 +922,10 @@ k_materialize(long long nc, int ns, double h, const double* __restrict__ map, S*
         const double nb = u0 - (u1 * dirD[s] + u2 * dirD[ns + s] + u3 * dirD[2 * ns + s]);
         const double nb3 = nb * nb * nb;
         Io = code * (n0c * nb3 * It + hQ) * rcp_pos((n0c + nb * ab * h) * nb3);  // nb > 0
-        *q = (S)Io;
       } else if (zero) {
         Io = 0.0;
-        *q = (S)0;
       }
+      bstore<S>(plane_rsrc(I + (long long)s * nc, pbytes), soff, (S)Io);
       const double Iq = (double)(S)Io;
       if (Rout)
         for (int m = 0; m < 10; ++m) R[m] += W16[s * 16 + m] * Iq;
@@ -930,6 +937,8 @@ k_materialize(long long nc, int ns, double h, const double* __restrict__ map, S*
         g[3] += dI * dirD[2 * ns + s];
       }
     }
+#pragma unroll
+    for (int u = 0; u < B; ++u) v[u] = vn[u];
   }
   if (Rout)
     for (int m = 0; m < 10; ++m) Rout[m * nc + c] = R[m];
