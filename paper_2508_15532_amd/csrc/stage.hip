@@ -689,9 +689,11 @@ k_stage(StageArgs a, StagePtrs p) {
     // branches and the advection term.  Flat: the sign of the direction
     // component is uniform over a face group, so each group takes one branch
     // (POS); at rest nu is applied once per cell in the divergence.
-    auto fpos = [&](auto pos_tag, const Face& fc, int rec, F nu, F vm1, F hL, F v0, F hR) -> F {
+    // dq = v0 - vm1 is the difference the slopes have already formed, so
+    // vm1 - v0 = -dq (exactly) costs nothing here.
+    auto fpos = [&](auto pos_tag, const Face& fc, int rec, F nu, F vm1, F hL, F v0, F hR, F dq) -> F {
       constexpr int POS = decltype(pos_tag)::value;
-      const F L = vm1 + hL, Rr = v0 - hR, D = vm1 - v0;
+      const F L = vm1 + hL, Rr = v0 - hR, D = -dq;
       F f;
       if (CURVED) {
         const F* r = GR + rec * 4;
@@ -707,9 +709,9 @@ k_stage(StageArgs a, StagePtrs p) {
     // upper minus lower face flux of the cell c2 from the values c0 .. c4 along the axis
     auto div1 = [&](auto pos, const Face& lo, const Face& hi, int rlo, int rhi, F nu, F c0, F c1, F c2,
                     F c3, F c4) -> F {
-      const F hm = half_slope<LIM>(c1 - c0, c2 - c1), h0 = half_slope<LIM>(c2 - c1, c3 - c2),
-              hp = half_slope<LIM>(c3 - c2, c4 - c3);
-      return fpos(pos, hi, rhi, nu, c2, h0, c3, hp) - fpos(pos, lo, rlo, nu, c1, hm, c2, h0);
+      const F d01 = c1 - c0, d12 = c2 - c1, d23 = c3 - c2, d34 = c4 - c3;
+      const F hm = half_slope<LIM>(d01, d12), h0 = half_slope<LIM>(d12, d23), hp = half_slope<LIM>(d23, d34);
+      return fpos(pos, hi, rhi, nu, c2, h0, c3, hp, d23) - fpos(pos, lo, rlo, nu, c1, hm, c2, h0, d12);
     };
     auto xpart = [&](auto pos) {
 #pragma unroll
@@ -725,12 +727,15 @@ k_stage(StageArgs a, StagePtrs p) {
                       pl[k][ty + 4][tx + 2]);
     };
     auto zpart = [&](auto pos) {
-      F sz[NW];
+      F dz[NW - 1], sz[NW];
 #pragma unroll
-      for (int j = 1; j <= TZ + 2; ++j) sz[j] = half_slope<LIM>(w[j] - w[j - 1], w[j + 1] - w[j]);
+      for (int j = 0; j + 1 < NW; ++j) dz[j] = w[j + 1] - w[j];
+#pragma unroll
+      for (int j = 1; j <= TZ + 2; ++j) sz[j] = half_slope<LIM>(dz[j - 1], dz[j]);
 #pragma unroll
       for (int f = 0; f <= TZ; ++f)
-        fz[f] = fpos(pos, fcz[f], NRX + NRY + f * TY + ty, nz, w[f + 1], sz[f + 1], w[f + 2], sz[f + 2]);
+        fz[f] = fpos(pos, fcz[f], NRX + NRY + f * TY + ty, nz, w[f + 1], sz[f + 1], w[f + 2], sz[f + 2],
+                     dz[f + 1]);
     };
     using TPos = std::integral_constant<int, 1>;
     using TNeg = std::integral_constant<int, 0>;
