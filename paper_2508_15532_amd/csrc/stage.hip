@@ -17,6 +17,8 @@
 // separate materialisation pass follows each stage.
 #include <hip/hip_runtime.h>
 
+#include <limits>
+
 #include <algorithm>
 #include <cmath>
 #include <type_traits>
@@ -71,6 +73,20 @@ template <int LIM, typename T>
 __device__ __forceinline__ T half_slope(T p, T q) {
   if (LIM == RT_LIM_MC) return med0(med0(p, q), T(0.25) * (p + q));
   return T(0.5) * med0(p, q);
+}
+
+// x > 0 and x < 0 for a value every lane holds (a direction component read
+// by a scalar load), from its bits: scalar comparisons, no vector compare
+template <typename T>
+__device__ __forceinline__ bool upos(T x) {
+  using B = typename std::conditional<sizeof(T) == 4, int, long long>::type;
+  return __builtin_bit_cast(B, x) > 0;
+}
+template <typename T>
+__device__ __forceinline__ bool uneg(T x) {
+  using B = typename std::conditional<sizeof(T) == 4, int, long long>::type;
+  const B b = __builtin_bit_cast(B, x);
+  return b < 0 && b != std::numeric_limits<B>::min();  // negative, not -0
 }
 
 // a read-only device array in the constant address space (loads at uniform
@@ -632,8 +648,8 @@ k_stage(StageArgs a, StagePtrs p) {
     // direction components along i1 (z), i2 (y), i3 (x)
     const F nz = dirF[s], ny = dirF[ns + s], nx = dirF[2 * ns + s];
     // flat zero-incoming: the outside sides that receive zero for this direction
-    const unsigned inc = (nz > F(0) ? 1u : 0u) | (nz < F(0) ? 2u : 0u) | (ny > F(0) ? 4u : 0u) |
-                         (ny < F(0) ? 8u : 0u) | (nx > F(0) ? 16u : 0u) | (nx < F(0) ? 32u : 0u);
+    const unsigned inc = (upos(nz) ? 1u : 0u) | (uneg(nz) ? 2u : 0u) | (upos(ny) ? 4u : 0u) |
+                         (uneg(ny) ? 8u : 0u) | (upos(nx) ? 16u : 0u) | (uneg(nx) ? 32u : 0u);
     const unsigned char* zs = CURVED ? p.zin + (long long)s * a.zin_stride : nullptr;
     auto ghost_zero = [&](unsigned flags6, int zoff) -> bool {
       if (CURVED) return zoff >= 0 && zs[zoff] != 0;
@@ -744,10 +760,9 @@ k_stage(StageArgs a, StagePtrs p) {
       ypart(TPos{});
       zpart(TPos{});
     } else {
-      auto up = [](F nu) { return __builtin_amdgcn_readfirstlane(nu > F(0) ? 1 : 0) != 0; };
-      if (up(nx)) xpart(TPos{}); else xpart(TNeg{});
-      if (up(ny)) ypart(TPos{}); else ypart(TNeg{});
-      if (up(nz)) zpart(TPos{}); else zpart(TNeg{});
+      if (upos(nx)) xpart(TPos{}); else xpart(TNeg{});
+      if (upos(ny)) ypart(TPos{}); else ypart(TNeg{});
+      if (upos(nz)) zpart(TPos{}); else zpart(TNeg{});
     }
 
     // 3. divergence, update, interaction sums
